@@ -1,0 +1,74 @@
+"""Prior draws (oracle side).
+
+Follows the prior of the paper's Table 1 (section 5): chirp mass and mass
+ratio uniform, luminosity distance uniform in volume (density proportional
+to D_L^2), inclination with a sine density, right ascension uniform,
+declination with a cosine density, coalescence phase uniform on (0, 2*pi),
+polarisation angle uniform on (0, pi).  The workload configurations replace
+the ranges of Table 1 and add aligned spins (uniform components), which the
+paper's section 5 says it leaves out for now.
+
+Readings where the paper is silent:
+  * inclination iota stands in for theta_JN (they coincide for aligned spins);
+  * right ascension is used as the Earth-fixed longitude (sidereal time 0);
+  * coalescence time t_c (seconds from the window start) is uniform on
+    [T - 1.5 s, T - 0.5 s): the merger lands 0.5-1.5 s before the window end;
+  * the background offset o (first background sample used by the sample,
+    identical for every detector) is uniform over every admissible start:
+    o = floor(u * (L_bg - P - N + 1)).
+
+Parameter rows (binary64, [12][B]):
+  0 M_c [Msun]  1 q = m2/m1  2 chi1  3 chi2  4 D_L [Mpc]  5 iota  6 alpha
+  7 delta  8 psi  9 phi_c  10 t_c [s]  11 reserved (0)
+Philox stream ids: the row index for rows 0-10, 12 for the offset.
+"""
+
+import math
+
+import numpy as np
+
+from .rng import philox_uniform
+
+PARAM_NAMES = ("mc", "q", "chi1", "chi2", "dl", "iota", "ra", "dec", "psi",
+               "phic", "tc", "reserved")
+N_PARAMS = 12
+OFFSET_STREAM = 12
+
+
+def sample_params(cfg, seed, first_index, B, L_bg):
+    """Draw B samples; returns (params float64 [12][B], offsets int64 [B]).
+
+    cfg keys used: mc, q, chi, dl (each a (lo, hi) pair), t_window,
+    psd_length, fs.
+    """
+    fs = float(cfg["fs"])
+    T = float(cfg["t_window"])
+    N = int(round(T * fs))
+    P = int(round(float(cfg["psd_length"]) * fs))
+    span = L_bg - P - N + 1
+    if span <= 0:
+        raise ValueError("background shorter than one PSD stretch plus window")
+    params = np.zeros((N_PARAMS, B), dtype=np.float64)
+    offsets = np.zeros(B, dtype=np.int64)
+    (mc_a, mc_b), (q_a, q_b) = cfg["mc"], cfg["q"]
+    (chi_a, chi_b), (dl_a, dl_b) = cfg["chi"], cfg["dl"]
+    for i in range(B):
+        g = first_index + i
+        u = [philox_uniform(seed, g, s) for s in range(11)]
+        params[0, i] = mc_a + u[0] * (mc_b - mc_a)
+        params[1, i] = q_a + u[1] * (q_b - q_a)
+        params[2, i] = chi_a + u[2] * (chi_b - chi_a)
+        params[3, i] = chi_a + u[3] * (chi_b - chi_a)
+        # uniform in volume: CDF (D^3 - a^3) / (b^3 - a^3)
+        params[4, i] = (dl_a ** 3 + u[4] * (dl_b ** 3 - dl_a ** 3)) ** (1.0 / 3.0)
+        # sine density on (0, pi): cos(iota) uniform on (-1, 1)
+        params[5, i] = math.acos(2.0 * u[5] - 1.0)
+        params[6, i] = 2.0 * math.pi * u[6]
+        # cosine density on (-pi/2, pi/2): sin(delta) uniform on (-1, 1)
+        params[7, i] = math.asin(2.0 * u[7] - 1.0)
+        params[8, i] = math.pi * u[8]
+        params[9, i] = 2.0 * math.pi * u[9]
+        params[10, i] = T - 1.5 + u[10] * 1.0
+        uo = philox_uniform(seed, g, OFFSET_STREAM)
+        offsets[i] = int(math.floor(uo * span))
+    return params, offsets
