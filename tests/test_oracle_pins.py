@@ -309,6 +309,45 @@ def test_remnant_and_ringdown_against_published_values():
     assert abs(af_small - 0.5) < 1e-4
 
 
+def _kerr_isco(a):
+    """Prograde ISCO of a Kerr black hole (Bardeen, Press & Teukolsky 1972):
+    radius, specific energy and specific angular momentum (M = 1)."""
+    z1 = 1 + (1 - a * a) ** (1 / 3) * ((1 + a) ** (1 / 3) + (1 - a) ** (1 / 3))
+    z2 = math.sqrt(3 * a * a + z1 * z1)
+    r = 3 + z2 - math.sqrt((3 - z1) * (3 + z1 + 2 * z2))
+    den = r ** 0.75 * math.sqrt(r ** 1.5 - 3 * r ** 0.5 + 2 * a)
+    E = (r ** 1.5 - 2 * r ** 0.5 + a) / den
+    L = (r * r - 2 * a * r ** 0.5 + a * a) / den
+    return r, E, L
+
+
+@pytest.mark.parametrize("a", [0.0, 0.3, 0.5])
+def test_final_spin_test_particle_limit_is_kerr_isco(a):
+    """For a small body on a spin-a hole, the spin changes to first order in
+    eta by eta (L_isco - 2 a E_isco) (plunge from the ISCO).  The fit is
+    quadratic in the spin, so it follows this limit to about 1 % up to
+    a ~ 0.6 and departs from it at higher spin."""
+    r, E, L = _kerr_isco(a)
+    if a == 0.0:
+        assert abs(r - 6.0) < 1e-12 and abs(L - 2 * math.sqrt(3)) < 1e-12
+    eps = 1e-6
+    af, _ = waveform.remnant(eps, a, 0.0)
+    eta = eps / (1 + eps) ** 2
+    a_tot = a / (1 + eps * eps)
+    slope = (af - a_tot) / eta
+    assert abs(slope - (L - 2 * a * E)) < 0.02
+
+
+def test_final_spin_spinning_equal_mass():
+    g = {r[0]: (float(r[1]), float(r[2])) for r in _golden_rows("black_hole_reference_values.txt")}
+    af, _ = waveform.remnant(1.0, 0.757, 0.757)
+    v, tol = g["final_spin_equal_mass_aligned_0757"]
+    assert abs(af - v) < tol
+    af, _ = waveform.remnant(1.0, -0.757, -0.757)
+    v, tol = g["final_spin_equal_mass_antialigned_0757"]
+    assert abs(af - v) < tol
+
+
 @pytest.mark.parametrize("mc,q,c1,c2", [(30.0, 1.0, 0.0, 0.0), (60.0, 0.3, 0.8, -0.5),
                                         (12.0, 0.9, -0.9, 0.9), (95.0, 0.13, 0.99, 0.99)])
 def test_imr_form_joins_are_smooth(mc, q, c1, c2):
@@ -578,3 +617,23 @@ def test_generate_sample_consistent_with_stages():
     z = oracle.derived_sizes(cfg)
     S = oracle.interp_psd(st["psd"][0], z["r"])
     np.testing.assert_allclose(out[0], spectral.whiten(st["y"][0], S, cfg["fs"], cfg["f_min"]))
+
+
+def test_window_follows_psd_stretch():
+    """An impulse just before o + P reaches the PSD and not the window; one
+    at o + P reaches the window and not the PSD (reading: the Welch stretch
+    immediately precedes the window, same offset in every detector)."""
+    cfg = inputs.config("pr1_plain")
+    z = oracle.derived_sizes(cfg)
+    o = 1000
+    zero = np.zeros((2, o + z["P"] + z["N"] + 10))
+    H = np.zeros((2, z["F"]), dtype=complex)
+    # periodic Hann vanishes at the first sample of a segment, so probe o + 1
+    for pos, in_psd in ((o + z["P"] - 1, True), (o + z["P"], False), (o + 1, True), (o - 1, False)):
+        bg = zero.copy()
+        bg[1, pos] = 1.0
+        psd = oracle.pipeline.sample_psd(cfg, bg, o)
+        y = oracle.inject(cfg, bg, o, H)
+        assert np.all(psd[0] == 0) and np.all(y[0] == 0)
+        assert (np.abs(psd[1]).max() > 0) == in_psd
+        assert (np.abs(y[1]).max() > 0) == (pos == o + z["P"])
