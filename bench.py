@@ -1,0 +1,224 @@
+"""Throughput of the on-the-fly training-data generator on one MI355X.
+
+A step is one whole batch of the paper-scale workload: 2048 samples, three
+detectors (H1, L1, V1), 8 s windows at 2048 Hz, IMR-form waveforms, a Welch
+PSD per (sample, detector) from the 64 s of background preceding its window.
+Steps run back to back on the resident background (2^27 samples per detector)
+with every input already in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "whitened 3-det 8s@2048Hz samples/sec (plain vs surrogate) + % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+WELCH_SRC = os.path.join(ROOT, "paper_2407_19048_amd", "csrc")
+
+
+def log(msg):
+    sys.stderr.write(msg + "\n")
+    sys.stderr.flush()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(WELCH_SRC)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(WELCH_SRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------ CPU baseline
+
+def _oracle_worker(args):
+    cfg, slices, params, budget_s = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import numpy as np  # noqa: F401
+    import oracle
+    done, t0 = 0, time.perf_counter()
+    while True:
+        for bg, p in zip(slices, params):
+            oracle.generate_sample(cfg, bg, p, 0)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                return done, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, bg, seed, B, budget_s, workers):
+    """The FP64 oracle on the same workload: `workers` processes, each
+    regenerating its share of a fixed sample set until the time budget."""
+    import numpy as np
+    import oracle
+    z = oracle.derived_sizes(cfg)
+    n_distinct = min(B, 4 * workers)
+    params, offs = oracle.sample_params(cfg, seed, 0, n_distinct, bg.shape[1])
+    slices = [np.ascontiguousarray(bg[:, o:o + z["P"] + z["N"]]) for o in offs]
+    jobs = []
+    for w in range(workers):
+        sel = list(range(w, n_distinct, workers))
+        jobs.append((cfg, [slices[i] for i in sel], [params[:, i] for i in sel], budget_s))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return dict(value=done / busy, unit="samples/s", cores=workers, kind="oracle",
+                sample="%d oracle samples (FP64 NumPy, %d distinct draws of the paper-scale "
+                       "workload) over %.1f s in %d processes, one thread each; %.1f s wall "
+                       "with start-up" % (done, n_distinct, busy, workers, wall))
+
+
+# ------------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--log2-bg", type=int, default=27)
+    ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this generator has no cross-GPU step "
+              "(samples are independent), and multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    from paper_2407_19048_amd import inputs
+
+    cfg = inputs.config("paper_scale", precision=args.precision)
+    B, K, W = args.batch, args.steps, args.warmup
+    n_det = len(cfg["det_ids"])
+    t0 = time.perf_counter()
+    bg_np = inputs.background(n_det, 1 << args.log2_bg, cfg["fs"], seed=1)
+    log("background %s generated in %.1f s" % (bg_np.shape, time.perf_counter() - t0))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(cfg, bg_np, 2, B, args.cpu_budget, workers)
+        log("cpu baseline: %.1f samples/s on %d cores" % (cpu["value"], cpu["cores"]))
+
+    import torch
+    from paper_2407_19048_amd import gwgen
+    gwgen.lib()
+    dev = torch.device("cuda:0")
+    bg = torch.from_numpy(bg_np).to(dev)
+    del bg_np
+    gen = gwgen.Generator(cfg)
+    z = gen.sizes
+    out = torch.empty((B, n_det, z["N"]), dtype=torch.float32, device=dev)
+    pf = torch.empty((12, B), dtype=torch.float32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    ws = gen.alloc_workspace(B, device=dev)
+    seed = 2
+
+    for i in range(W):
+        gen.generate_batch(seed, i, B, bg, out, ws, pf, status)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t0 = time.perf_counter()
+    for i in range(K):
+        gen.generate_batch(seed, W + i, B, bg, out, ws, pf, status)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (K, elapsed))
+    value = B * K / elapsed
+    ms_step = 1e3 * elapsed / K
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("non-finite output")
+
+    # dominant kernel: segmented Welch, timed on its own with HIP events on the
+    # stream the library launches on (torch's current stream)
+    _, offs = gen.workspace_views(ws, B)
+    psd = torch.empty((B, n_det, z["Fw"]), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        gen.welch_psd(bg, offs, psd)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(K):
+        gen.welch_psd(bg, offs, psd)
+    ev1.record()
+    torch.cuda.synchronize()
+    welch_ms = ev0.elapsed_time(ev1) / K
+    # algorithmic bytes per launch: every sample reads its P-sample stretch in
+    # each detector once and writes its PSD
+    welch_bytes = B * n_det * (z["P"] + z["Fw"]) * 4
+    welch_gbs = welch_bytes / (welch_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_welch", "paper_scale_B%d" % B)
+
+    # whole step, algorithmic bytes per sample: D (P + N) reads + D N writes
+    step_bytes = B * n_det * ((z["P"] + z["N"]) + z["N"]) * 4
+    step_gbs = step_bytes / (elapsed / K) / 1e9
+    log("step %.3f ms (%.0f GB/s algorithmic, %.1f %% of HBM peak); welch %.3f ms (%.0f GB/s)"
+        % (ms_step, step_gbs, 100 * step_gbs / HBM_PEAK_GBS, welch_ms, welch_gbs))
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper_scale: batch 2048, H1+L1+V1, 8 s windows at 2048 Hz, IMR-form "
+                        "waveforms, per-sample Welch PSD over 64 s (2 s Hann, 1 s overlap), "
+                        "plain path",
+            "global_batch": B, "window_samples": z["N"], "psd_stretch_samples": z["P"],
+            "background_samples_per_det": int(bg.shape[1]), "precision_mode": args.precision,
+            "path": "plain",
+            "step_hbm_frac_algorithmic": round(step_gbs / HBM_PEAK_GBS, 4),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_welch",
+            "achieved": round(welch_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(welch_gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * gwgen.h -- C ABI of libgwgen.so, an on-the-fly training-data generator for
+ * likelihood-free inference of binary-black-hole mergers on AMD MI355X
+ * (gfx950).
+ *
+ * The generator follows section 3.2 of "Rapid Likelihood Free Inference of
+ * Compact Binary Coalescences using Accelerated Hardware" (AMPLFI).  A long
+ * detector background is kept resident in device memory.  Each batch draws
+ * parameters from the priors of Table 1 (section 5) and generates
+ * frequency-domain plus/cross waveforms (section 3.1).  It projects them onto
+ * the detectors with antenna patterns and arrival-time delays (the on-device
+ * projection that section 6 describes), injects them into the background, and
+ * estimates a noise PSD.  Finally it whitens the strain and emits the windows
+ * together with the parameters.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are caller-owned DEVICE pointers (for example, memory
+ *     allocated by PyTorch).  The library never frees, keeps or reallocates
+ *     them.  Pointers must be 16-byte aligned unless stated otherwise.
+ *   - Work is queued asynchronously on `stream`.  Nothing synchronises;
+ *     results are ready once the caller synchronises that stream.
+ *   - Sizes, null pointers, alignment and configuration are checked on the
+ *     host before anything is launched.  On a failed check the call returns
+ *     GW_EINVAL and launches nothing.  A failed launch returns GW_EHIP;
+ *     gw_last_error() then returns HIP's message.
+ *   - A bad DATA value (a NaN in the background, a PSD bin <= 0) never fails
+ *     a call.  Affected bins are dropped from the whitened output and a
+ *     per-sample status bit is set (GW_STATUS_*).
+ *   - A gw_ctx is not thread-safe.  Use one per host thread / stream.
+ *   - Strain is in units of 2^70 x dimensionless strain.  This exact power of
+ *     two keeps PSD values inside binary32 range.  The PSD is in
+ *     (2^70)^2 / Hz.  The whitened output is dimensionless and does not depend
+ *     on the scale.
+ *   - Complex arrays are interleaved (re, im) binary32 pairs.
+ */
+#ifndef GWGEN_H
+#define GWGEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gw_status;
+#define GW_OK            0
+#define GW_EINVAL       -1  /* bad argument or configuration               */
+#define GW_ENOMEM       -2  /* device allocation failed (gw_create only)    */
+#define GW_EHIP         -3  /* a HIP call or kernel launch failed           */
+#define GW_EUNSUPPORTED -4  /* valid, but not supported by this build       */
+
+/* Per-sample status bits (uint32), OR-ed over the sample's detectors. */
+#define GW_STATUS_NONFINITE_PSD  1u  /* a PSD bin was NaN/Inf (bad background) */
+#define GW_STATUS_NONPOSITIVE_PSD 2u /* a kept PSD bin was <= 0                */
+#define GW_STATUS_NONFINITE_DATA 4u  /* a window value was NaN/Inf             */
+#define GW_STATUS_CUT_AT_NYQUIST 8u  /* waveform cut-off above fs/2            */
+
+#define GW_N_PARAMS 12
+#define GW_MAX_DET 4
+
+/* Generator configuration (plain data, copied by gw_create).
+ * Priors: M_c, q, chi and D_L ranges replace those of Table 1.  The angles
+ * follow Table 1: iota with a sine density, RA uniform on (0, 2 pi),
+ * declination with a cosine density, phi_c uniform on (0, 2 pi), psi uniform
+ * on (0, pi).  t_c is uniform on [T - 1.5 s, T - 0.5 s).
+ * Sizes: N = t_window*fs is the window length.  P = psd_length*fs is the PSD
+ * stretch preceding the window.  L = fftlen*fs is the Welch segment length and
+ * S = (fftlen - overlap)*fs is the segment stride.  K = (P - L)/S + 1
+ * segments are averaged.  Constraints: N and L are powers of two,
+ * 2^11 <= N <= 2^15, 2^11 <= L <= 2^12, N/L is an integer, and
+ * (P - L) is a multiple of S.  The stride must be L/2 (50 % overlap). */
+typedef struct gw_config {
+  int32_t n_det;               /* 1..4 */
+  int32_t det_id[GW_MAX_DET];  /* 0 = H1, 1 = L1, 2 = V1 */
+  double  fs;                  /* sample rate [Hz] */
+  double  t_window;            /* window length T [s] */
+  double  psd_length;          /* Welch stretch [s] */
+  double  fftlen;              /* Welch segment [s] */
+  double  overlap;             /* Welch overlap [s] */
+  double  f_min;               /* waveform start and whitening low cut [Hz] */
+  int32_t approximant;         /* 0 TaylorF2 3.5PN, 1 IMR-form */
+  int32_t precision;           /* 0 binary32 throughout, 1 mixed (binary64
+                                  phase and Welch accumulation), 2 binary64 */
+  double  mc[2], q[2], chi[2], dl[2];   /* prior ranges [Msun], [], [], [Mpc] */
+} gw_config;
+
+typedef struct gw_ctx gw_ctx;
+
+/* Create a context: validate the configuration, build detector geometry and
+ * twiddle/power tables on the current HIP device.  Allocates device memory
+ * (about 0.5 MB); this is the only entry point that allocates. */
+gw_status gw_create(const gw_config* cfg, gw_ctx** out);
+gw_status gw_destroy(gw_ctx* ctx);
+const char* gw_strerror(gw_status s);
+/* Message of the last failure seen by this context (HIP string or a
+ * description of the rejected argument).  Valid until the next call. */
+const char* gw_last_error(const gw_ctx* ctx);
+
+/* gw_query keys. */
+#define GW_Q_N        0   /* window samples                          */
+#define GW_Q_F        1   /* window rfft bins N/2+1                  */
+#define GW_Q_P        2   /* PSD stretch samples                     */
+#define GW_Q_L        3   /* Welch segment samples                   */
+#define GW_Q_K        4   /* Welch segments                          */
+#define GW_Q_FW       5   /* Welch bins L/2+1                        */
+#define GW_Q_NDET     6
+#define GW_Q_NPARAMS  7
+gw_status gw_query(const gw_ctx* ctx, int32_t key, int64_t* value);
+/* Bytes of device workspace gw_generate_batch needs for batch size B. */
+gw_status gw_workspace_size(const gw_ctx* ctx, int64_t B, int64_t* bytes);
+
+/* sample_params -- prior draws (Table 1, section 5; ranges from gw_config).
+ * Draws use the Philox4x32-10 counter-based generator (Salmon et al. 2011).
+ * The key is (seed lo, seed hi) and the counter is (g lo, g hi, stream, 0),
+ * where g = first_index + i is the global sample index.  Output is therefore
+ * independent of how a run is split into batches.
+ * params: double [12][B] rows {M_c, q, chi1, chi2, D_L, iota, RA, dec, psi,
+ *         phi_c, t_c, 0}.
+ * offset: int64 [B] first background sample of sample i, uniform on
+ *         [0, L_bg - P - N].  The PSD stretch is [o, o+P); the window is
+ *         [o+P, o+P+N).
+ * Requires L_bg >= P + N and B >= 0 (B == 0 is a no-op). */
+gw_status sample_params(gw_ctx* ctx, uint64_t seed, uint64_t first_index,
+                        int64_t B, int64_t L_bg, double* params,
+                        int64_t* offset, hipStream_t stream);
+
+/* gen_fd_waveform -- frequency-domain plus/cross polarisations (section
+ * 3.1) on f_k = k/T, k = 0..N/2, with t_c = 0.  The result is in
+ * continuous-transform units [2^70 s].  It is zero outside
+ * f_min <= f_k < f_cut and at k = 0 and k = N/2.  TaylorF2 has
+ * f_cut = f_ISCO; IMR-form has f_cut = 0.2/M.
+ * params: double [12][B] as written by sample_params.
+ * hp, hc: interleaved complex float [B][N/2+1]. */
+gw_status gen_fd_waveform(gw_ctx* ctx, const double* params, int64_t B,
+                          float* hp, float* hc, hipStream_t stream);
+
+/* project_detectors -- antenna patterns F+, Fx and geocentric delay dt_d for
+ * each configured detector, from (RA, dec, psi).  Applied on device as the
+ * paper's section 6 describes.  Output:
+ *   hdet[b][d][k] = fs (F+ hp + Fx hc) exp(-2 pi i f_k (t_c + dt_d)),
+ * i.e. DFT coefficients of the detector strain on the window grid.
+ * hdet: interleaved complex float [B][n_det][N/2+1]. */
+gw_status project_detectors(gw_ctx* ctx, const double* params,
+                            const float* hp, const float* hc, int64_t B,
+                            float* hdet, hipStream_t stream);
+
+/* inject -- add each projected signal to its background window (section
+ * 3.2): strain[b][d][n] = bg[d][o_b + P + n] + irfft_N(hdet[b][d])[n].
+ * bg: float [n_det][L_bg] (row pitch L_bg, 4-byte alignment suffices).
+ * offset: int64 [B] (host does not read it; values must lie in
+ * [0, L_bg - P - N]).  strain: float [B][n_det][N]. */
+gw_status inject(gw_ctx* ctx, const float* bg, int64_t L_bg,
+                 const int64_t* offset, const float* hdet, int64_t B,
+                 float* strain, hipStream_t stream);
+
+/* welch_psd -- noise PSD fitted to background (section 3.2).  One estimate
+ * is made per (sample, detector) from the P samples [o_b, o_b + P) preceding
+ * the window.  Welch's method uses K periodic-Hann segments of L samples at
+ * stride S, no detrending, a mean over segments, and one-sided density
+ * scaling:
+ *   psd[k] = c_k/(K fs sum w^2) sum_s |rfft(w seg_s)[k]|^2,
+ * with c_k = 2 except at DC and Nyquist, where c_k = 1.
+ * psd: float [B][n_det][L/2+1]. */
+gw_status welch_psd(gw_ctx* ctx, const float* bg, int64_t L_bg,
+                    const int64_t* offset, int64_t B, float* psd,
+                    hipStream_t stream);
+
+/* whiten -- whiten each window with its PSD (section 3.2).  The PSD is
+ * interpolated linearly onto the window grid (ratio N/L), then
+ *   out = irfft(rfft(strain) / sqrt(fs S(f_k)/2)),
+ * keeping f_k >= f_min and 0 < k < N/2.  Bins with a non-finite or
+ * non-positive PSD are dropped and flagged.
+ * strain, out: float [B][n_det][N] (may alias).  psd: float [B][n_det][L/2+1].
+ * status: uint32 [B] or NULL.  It is overwritten with the GW_STATUS_* bits. */
+gw_status whiten(gw_ctx* ctx, const float* strain, const float* psd,
+                 int64_t B, float* out, uint32_t* status, hipStream_t stream);
+
+/* gw_generate_batch -- the whole per-batch path (section 3.2) in three
+ * launches: prior draws, per-(sample, detector) Welch PSDs, then one fused
+ * kernel per (sample, detector).  The fused kernel loads the noise window,
+ * transforms it, adds the in-register waveform + projection + time shift,
+ * whitens, inverse-transforms and stores.  The result equals
+ * sample_params -> gen_fd_waveform -> project_detectors -> inject ->
+ * welch_psd -> whiten.  The global sample indices are
+ * batch_index*B .. batch_index*B + B - 1.
+ * out:        float [B][n_det][N] whitened strain.
+ * params_f32: float [12][B] parameters for the trainer, or NULL.
+ * status:     uint32 [B] or NULL.
+ * workspace:  device memory of at least gw_workspace_size(B) bytes.  It
+ *             holds params (double [12][B]), offsets and PSDs.  After the
+ *             call, the first 96*B bytes hold params as double [12][B] and the
+ *             next 8*B bytes hold the int64 offsets. */
+gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
+                            int64_t B, const float* bg, int64_t L_bg,
+                            float* out, float* params_f32, uint32_t* status,
+                            void* workspace, int64_t workspace_bytes,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWGEN_H */

@@ -1,0 +1,234 @@
+// Block-level FFT for gfx950: one workgroup transforms NC complex points,
+// each of NT = NC/16 threads holding 16 of them in registers.
+//
+// Structure: Stockham auto-sort radix-R passes (radix 16 first, then 16s,
+// then one 2/4/8 pass when NC is not a power of 16).  Data is exchanged
+// between passes through LDS, in separate real/imaginary planes padded by one
+// word every 16 so that each pass's reads and writes are free of bank
+// conflicts.
+//
+// Register layout of a thread t:
+//   before the first pass   v[r]     = x[t + NT*r]                (r < 16)
+//   after the last pass     v[m*R+r] = X[t + NT*m + r*NC/R]       (R = last radix)
+// A thread therefore reads and writes coalesced global memory at both ends,
+// with no transpose.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gw {
+
+template <class T> struct cpx { T x, y; };
+
+template <class T> __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T> __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T> __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
+template <class T> __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by DIR*i (DIR = -1: by -i, DIR = +1: by +i)
+template <int DIR, class T> __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+  if constexpr (DIR < 0) return {a.y, -a.x};
+  else return {-a.y, a.x};
+}
+// a * w for DIR = -1, a * conj(w) for DIR = +1 (w is a forward twiddle)
+template <int DIR, class T> __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cpx<T> w) {
+  if constexpr (DIR < 0) return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+  else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int NC> struct LdsSize { static constexpr int value = NC + NC / 16; };
+
+// a * exp(DIR * 2 pi i m / 16), m a compile-time constant
+template <int M, int DIR, class T> __device__ __forceinline__ cpx<T> w16(cpx<T> a) {
+  constexpr int m = ((M % 16) + 16) % 16;
+  constexpr T C1 = T(0.92387953251128675613), S1 = T(0.38268343236508977173);
+  constexpr T R2 = T(0.70710678118654752440);
+  if constexpr (m == 0) return a;
+  else if constexpr (m == 4) return mul_i<DIR>(a);
+  else if constexpr (m == 8) return {-a.x, -a.y};
+  else if constexpr (m == 12) return mul_i<-DIR>(a);
+  else if constexpr (m == 2 || m == 6 || m == 10 || m == 14) {
+    // exp(DIR i pi m/8) = (cx + DIR i sy)/sqrt2 with cx, sy in {+1,-1}
+    constexpr T cx = (m == 2 || m == 14) ? T(1) : T(-1);
+    constexpr T sy = (m == 2 || m == 6) ? T(1) : T(-1);
+    constexpr T s = T(DIR) * sy;
+    return {(a.x * cx - a.y * s) * R2, (a.y * cx + a.x * s) * R2};
+  } else {
+    // angle = quad * pi/2 + phi, phi = (m & 3) * pi/8 with (m & 3) in {1, 3}
+    constexpr int q = m & 3;
+    constexpr T cphi = (q == 1) ? C1 : S1, sphi = (q == 1) ? S1 : C1;
+    constexpr int quad = m >> 2;
+    constexpr T c = quad == 0 ? cphi : quad == 1 ? -sphi : quad == 2 ? -cphi : sphi;
+    constexpr T sn = quad == 0 ? sphi : quad == 1 ? cphi : quad == 2 ? -sphi : -cphi;
+    constexpr T s = T(DIR) * sn;
+    return {a.x * c - a.y * s, a.y * c + a.x * s};
+  }
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft2(cpx<T>* a) {
+  cpx<T> t0 = a[0];
+  a[0] = cadd(t0, a[1]);
+  a[1] = csub(t0, a[1]);
+}
+
+template <int DIR, class T> __device__ __forceinline__ void dft4(cpx<T>& a0, cpx<T>& a1, cpx<T>& a2, cpx<T>& a3) {
+  cpx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_i<DIR>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+template <int DIR, class T> __device__ __forceinline__ void dft4(cpx<T>* a) { dft4<DIR>(a[0], a[1], a[2], a[3]); }
+
+template <int DIR, class T> __device__ __forceinline__ void dft8(cpx<T>* a) {
+  cpx<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  cpx<T> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  o1 = w16<2, DIR>(o1);
+  o2 = w16<4, DIR>(o2);
+  o3 = w16<6, DIR>(o3);
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+
+// 16-point DFT as 4 x 4: X[k1 + 4 k2] = sum_n2 W4^(n2 k2) W16^(n2 k1) DFT4_n1(a[4 n1 + n2])[k1]
+template <int DIR, class T> __device__ __forceinline__ void dft16(cpx<T>* a) {
+  dft4<DIR>(a[0], a[4], a[8], a[12]);
+  dft4<DIR>(a[1], a[5], a[9], a[13]);
+  dft4<DIR>(a[2], a[6], a[10], a[14]);
+  dft4<DIR>(a[3], a[7], a[11], a[15]);
+  // after this, a[n2 + 4 k1] holds Y_{n2}[k1]
+  a[5] = w16<1, DIR>(a[5]);
+  a[9] = w16<2, DIR>(a[9]);
+  a[13] = w16<3, DIR>(a[13]);
+  a[6] = w16<2, DIR>(a[6]);
+  a[10] = w16<4, DIR>(a[10]);
+  a[14] = w16<6, DIR>(a[14]);
+  a[7] = w16<3, DIR>(a[7]);
+  a[11] = w16<6, DIR>(a[11]);
+  a[15] = w16<9, DIR>(a[15]);
+  dft4<DIR>(a[0], a[1], a[2], a[3]);
+  dft4<DIR>(a[4], a[5], a[6], a[7]);
+  dft4<DIR>(a[8], a[9], a[10], a[11]);
+  dft4<DIR>(a[12], a[13], a[14], a[15]);
+  // now a[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4x4 index
+  cpx<T> t;
+  t = a[1]; a[1] = a[4]; a[4] = t;
+  t = a[2]; a[2] = a[8]; a[8] = t;
+  t = a[3]; a[3] = a[12]; a[12] = t;
+  t = a[6]; a[6] = a[9]; a[9] = t;
+  t = a[7]; a[7] = a[13]; a[13] = t;
+  t = a[11]; a[11] = a[14]; a[14] = t;
+}
+
+template <int R, int DIR, class T> __device__ __forceinline__ void dftR(cpx<T>* a) {
+  if constexpr (R == 16) dft16<DIR>(a);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 4) dft4<DIR>(a);
+  else dft2<DIR>(a);
+}
+
+// Radix plan: NP16 radix-16 passes followed by one pass of radix RL (1: none).
+template <int NC> struct FftPlan {
+  static constexpr int NP16 = (NC >= 65536) ? 4 : (NC >= 4096) ? 3 : (NC >= 256) ? 2 : 1;
+  static constexpr int RL = NC / (NP16 == 4 ? 65536 : NP16 == 3 ? 4096 : NP16 == 2 ? 256 : 16);
+  static constexpr int NPASS = NP16 + (RL > 1 ? 1 : 0);
+  static constexpr int RLAST = RL > 1 ? RL : 16;
+  static constexpr int NT = NC / 16;
+  static_assert(NC == 2048 || NC == 4096 || NC == 8192 || NC == 16384, "unsupported FFT size");
+};
+
+template <int NC, int PASS> struct PassInfo {
+  using P = FftPlan<NC>;
+  static constexpr int R = (PASS < P::NP16) ? 16 : P::RL;
+  static constexpr int NS = (PASS == 0) ? 1 : (PASS == 1) ? 16 : (PASS == 2) ? 256 : 4096;
+};
+
+// Output bin held in element e after the last pass.
+template <int NC> __device__ __forceinline__ int fft_out_index(int t, int e) {
+  constexpr int R = FftPlan<NC>::RLAST, NT = FftPlan<NC>::NT;
+  return t + NT * (e / R) + (e % R) * (NC / R);
+}
+
+// Twiddle providers: return the forward twiddle exp(-2 pi i r k / (NS R)).
+// Table form: tw[n] = exp(-2 pi i n / NC).
+template <class T, int NC> struct TableTwiddle {
+  const cpx<T>* __restrict__ tw;
+  template <int PASS> __device__ __forceinline__ cpx<T> get(int m, int r, int k) const {
+    constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS;
+    return tw[(r * k) * (NC / (NS * R))];
+  }
+};
+
+// One Stockham pass.  READ: take input from LDS (else registers already hold
+// it).  WRITE: scatter the output to LDS (else it stays in registers in the
+// final layout).  A barrier separates this pass's LDS reads from its writes;
+// the caller must ensure the LDS buffer is free before a pass that WRITEs
+// without READing.
+template <class T, int NC, int PASS, int DIR, bool READ, bool WRITE, class TW>
+__device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
+  constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS;
+  constexpr int NT = NC / 16, NB = 16 / R, STRIDE = NC / R;
+  if constexpr (READ) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+      const int j = t + NT * m;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lpad(j + r * STRIDE);
+        v[m * R + r] = {sre[i], sim[i]};
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    const int j = t + NT * m;
+    if constexpr (NS > 1) {
+      const int k = j & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[m * R + r] = twmul<DIR>(v[m * R + r], tw.template get<PASS>(m, r, k));
+    }
+    dftR<R, DIR>(v + m * R);
+  }
+  if constexpr (WRITE) {
+    if constexpr (READ) __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+      const int j = t + NT * m;
+      const int k = j & (NS - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lpad(base + r * NS);
+        sre[i] = v[m * R + r].x;
+        sim[i] = v[m * R + r].y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Whole transform.  FIRST_FROM_LDS: the first pass reads its input from LDS
+// in natural order (else v holds it as v[r] = x[t + NT r]).  The result stays
+// in registers in the final layout (see fft_out_index).  Ends with LDS still
+// being read by other threads: barrier before reusing it.
+template <class T, int NC, int DIR, bool FIRST_FROM_LDS, class TW>
+__device__ __forceinline__ void block_fft(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
+  using P = FftPlan<NC>;
+  fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true>(v, sre, sim, t, tw);
+  if constexpr (P::NPASS == 3) {
+    fft_pass<T, NC, 1, DIR, true, true>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 2, DIR, true, false>(v, sre, sim, t, tw);
+  } else {
+    fft_pass<T, NC, 1, DIR, true, true>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 2, DIR, true, true>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 3, DIR, true, false>(v, sre, sim, t, tw);
+  }
+}
+
+}  // namespace gw

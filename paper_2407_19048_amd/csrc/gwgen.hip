@@ -1,0 +1,858 @@
+// libgwgen.so: HIP kernels for gfx950 and the C ABI declared in gwgen.h.
+//
+// Kernels (grid / block):
+//   k_sample_params    ceil(B/256) / 256      prior draws, one thread per sample
+//   k_gen_fd_waveform  (ceil(F/256), B) / 256 plus/cross on the window grid
+//   k_project          (ceil(F/256), B) / 256 detector projection + time shift
+//   k_inject           B*D / (N/32)           irfft of the projected signal + noise
+//   k_welch            B*D / (L/16)           segmented Welch PSD, one block per
+//                                             (sample, detector)
+//   k_window<SRC>      B*D / (N/32)           rfft -> (+ signal) -> whiten -> irfft;
+//                                             SRC 0 reads strain (whiten), SRC 1
+//                                             reads the background and generates
+//                                             the signal in registers (fused)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gw_fft.hpp"
+#include "gw_physics.hpp"
+#include "../../include/gwgen.h"
+
+using namespace gw;
+
+namespace {
+
+// ------------------------------------------------------------ prior draws
+struct SampleArgs {
+  DevCfg cf;
+  uint64_t seed, first;
+  int64_t B, span;
+  double* params;
+  int64_t* offset;
+  float* params_f32;
+  uint32_t* status;
+};
+
+__global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
+#pragma clang fp contract(off)
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= a.B) return;
+  const uint64_t g = a.first + uint64_t(i);
+  const DevCfg& c = a.cf;
+  double u[11];
+#pragma unroll
+  for (int s = 0; s < 11; ++s) u[s] = philox_uniform(a.seed, g, uint32_t(s));
+  const double uo = philox_uniform(a.seed, g, 12u);
+  double p[12];
+  p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
+  p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
+  p[2] = c.chi[0] + u[2] * (c.chi[1] - c.chi[0]);
+  p[3] = c.chi[0] + u[3] * (c.chi[1] - c.chi[0]);
+  const double a3 = c.dl[0] * c.dl[0] * c.dl[0], b3 = c.dl[1] * c.dl[1] * c.dl[1];
+  p[4] = pow(a3 + u[4] * (b3 - a3), 1.0 / 3.0);
+  p[5] = acos(2.0 * u[5] - 1.0);
+  p[6] = 2.0 * kPi * u[6];
+  p[7] = asin(2.0 * u[7] - 1.0);
+  p[8] = kPi * u[8];
+  p[9] = 2.0 * kPi * u[9];
+  p[10] = c.T - 1.5 + u[10] * 1.0;
+  p[11] = 0.0;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) a.params[r * a.B + i] = p[r];
+  a.offset[i] = int64_t(floor(uo * double(a.span)));
+  if (a.params_f32) {
+#pragma unroll
+    for (int r = 0; r < 12; ++r) a.params_f32[r * a.B + i] = float(p[r]);
+  }
+  if (a.status) {
+    const double eta = p[1] / ((1.0 + p[1]) * (1.0 + p[1]));
+    const double Ms = p[0] * pow(eta, -0.6) * kMsunSec;
+    const double f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
+    a.status[i] = f_cut > 0.5 * c.fs ? GW_STATUS_CUT_AT_NYQUIST : 0u;
+  }
+}
+
+// -------------------------------------------------------- plus / cross
+struct WaveArgs {
+  DevCfg cf;
+  const double* params;
+  int64_t B;
+  const double* kcbrt;
+  const double* lnk3;
+  float* hp;
+  float* hc;
+};
+
+template <class TP, bool FULL>
+__global__ __launch_bounds__(256) void k_gen_fd_waveform(WaveArgs a) {
+  __shared__ WfScalars w;
+  const int64_t b = blockIdx.y;
+  if (threadIdx.x == 0) wf_setup(a.params, a.B, b, a.cf, w);
+  __syncthreads();
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int F = a.cf.F;
+  if (k >= F) return;
+  float2 hp = {0.f, 0.f}, hc = {0.f, 0.f};
+  if (k > 0 && k >= a.cf.kmin && k < w.kend) {
+    const double kc = a.kcbrt[k], lk = a.lnk3[k];
+    TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst);
+    rev = frac1(rev);
+    TP s, c;
+    sincospi_t(TP(2) * rev, &s, &c);
+    const TP A = wf_amplitude<TP>(w, k, kc, a.cf.invT);
+    const TP cp = A * TP(0.5) * (TP(1) + TP(w.cosi) * TP(w.cosi));
+    const TP cx = A * TP(w.cosi);
+    // h+ = A cp e^{-i Psi};  hx = -i A cx e^{-i Psi}
+    hp = {float(cp * c), float(-cp * s)};
+    hc = {float(-cx * s), float(-cx * c)};
+  }
+  reinterpret_cast<float2*>(a.hp)[b * F + k] = hp;
+  reinterpret_cast<float2*>(a.hc)[b * F + k] = hc;
+}
+
+// ------------------------------------------------------------ projection
+struct ProjArgs {
+  DevCfg cf;
+  const double* params;
+  int64_t B;
+  const float* hp;
+  const float* hc;
+  float* hdet;
+};
+
+template <class TP>
+__global__ __launch_bounds__(256) void k_project(ProjArgs a) {
+  __shared__ DetScalars ds[GW_MAX_DET];
+  const int64_t b = blockIdx.y;
+  const int D = a.cf.n_det;
+  if (threadIdx.x < D) {
+    const int64_t B = a.B;
+    ds[threadIdx.x] = det_response(a.cf.det[threadIdx.x], a.params[6 * B + b], a.params[7 * B + b],
+                                   a.params[8 * B + b], a.params[10 * B + b]);
+  }
+  __syncthreads();
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int F = a.cf.F;
+  if (k >= F) return;
+  const float2 hp = reinterpret_cast<const float2*>(a.hp)[b * F + k];
+  const float2 hc = reinterpret_cast<const float2*>(a.hc)[b * F + k];
+  for (int d = 0; d < D; ++d) {
+    const TP rev = frac1(TP(k) * TP(ds[d].tau * a.cf.invT));
+    float s, c;
+    sincospif(float(2 * rev), &s, &c);
+    const float fp = float(ds[d].fp), fx = float(ds[d].fx), fs = float(a.cf.fs);
+    const float2 h = {fs * (fp * hp.x + fx * hc.x), fs * (fp * hp.y + fx * hc.y)};
+    // h * e^{-i phi}
+    reinterpret_cast<float2*>(a.hdet)[(b * D + d) * F + k] = {h.x * c + h.y * s, h.y * c - h.x * s};
+  }
+}
+
+// ---------------------------------------- window kernels (FFT of length N)
+struct WinArgs {
+  DevCfg cf;
+  const float* src;       // strain [B][D][N] (SRC 0, 2) or background (SRC 1)
+  int64_t L_bg;
+  const float* bg;        // background for inject (SRC 2)
+  const int64_t* offset;
+  const double* params;
+  int64_t B;
+  const float* psd;       // [B][D][Fw]
+  float* out;
+  uint32_t* status;
+  const double* kcbrt;
+  const double* lnk3;
+  const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
+  const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
+};
+
+// Whitening factor for window bin k in [0, N/2]; sets status bits.
+template <class T>
+__device__ __forceinline__ T whiten_gain(const WinArgs& a, const float* psd, int k, int NC, uint32_t& flag) {
+  if (k == 0 || k >= NC || k < a.cf.kmin) return T(0);
+  const int r = a.cf.ratio;
+  const int i = k / r;
+  const T tt = T(k - i * r) / T(r);
+  const T S = (T(1) - tt) * T(psd[i]) + tt * T(psd[i + 1]);
+  if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
+  if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
+  return T(1) / sqrt_t(T(a.cf.fs) * S * T(0.5));
+}
+
+// Projected signal (DFT coefficients) at window bin k, generated in registers.
+template <class T, class TP, bool FULL>
+__device__ __forceinline__ cpx<T> signal_bin(const WinArgs& a, const WfScalars& w, T cpl, T cxx, double tauT, int k) {
+  if (k <= 0 || k < a.cf.kmin || k >= w.kend) return {T(0), T(0)};
+  const double kc = a.kcbrt[k], lk = a.lnk3[k];
+  TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
+  rev = frac1(rev);
+  T s, c;
+  sincospi_t(T(2) * T(rev), &s, &c);
+  const T A = T(a.cf.fs) * wf_amplitude<T>(w, k, kc, a.cf.invT);
+  // fs A (cpl - i cxx)(c - i s)
+  return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
+}
+
+// SRC 0: whiten strain.  SRC 1: fused background + signal + whiten.
+// SRC 2: inject (out = bg window + irfft(hdet)); src is hdet [B][D][N/2+1].
+template <class T, class TP, bool FULL, int NC, int SRC>
+__global__ __launch_bounds__(NC / 16) void k_window(WinArgs a) {
+  constexpr int NT = NC / 16;
+  constexpr int LS = LdsSize<NC>::value;
+  __shared__ T lds[2 * LS];
+  __shared__ WfScalars wsh;
+  __shared__ DetScalars dsh;
+  __shared__ uint32_t sflag;
+  T* sre = lds;
+  T* sim = lds + LS;
+  const int t = threadIdx.x;
+  const int64_t bd = blockIdx.x;
+  const int D = a.cf.n_det;
+  const int64_t b = bd / D;
+  const int d = int(bd - b * D);
+  const int N = 2 * NC;
+  const cpx<T>* twr = reinterpret_cast<const cpx<T>*>(a.twr);
+  TableTwiddle<T, NC> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
+  cpx<T> v[16];
+  uint32_t flag = 0;
+  if (t == 0) sflag = 0;
+
+  if constexpr (SRC != 2) {
+    const float* x = (SRC == 0) ? a.src + bd * N : a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = t + NT * r;
+      v[r] = {T(x[2 * n]), T(x[2 * n + 1])};
+    }
+    if constexpr (SRC == 1) {
+      if (t == 0) {
+        wf_setup(a.params, a.B, b, a.cf, wsh);
+        dsh = det_response(a.cf.det[d], wsh.ra, wsh.dec, wsh.psi, wsh.tc);
+      }
+    }
+    block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = lpad(fft_out_index<NC>(t, e));
+      sre[i] = v[e].x;
+      sim[i] = v[e].y;
+    }
+    __syncthreads();
+  }
+
+  const float* psd = a.psd + bd * a.cf.Fw;
+  T cpl = T(0), cxx = T(0);
+  double tauT = 0.0;
+  if constexpr (SRC == 1) {
+    cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
+    cxx = T(dsh.fx * wsh.cosi);
+    tauT = dsh.tau * a.cf.invT;
+  }
+  const float2* hsrc = (SRC == 2) ? reinterpret_cast<const float2*>(a.src) + bd * (NC + 1) : nullptr;
+
+  // pairs (k, NC - k) for k in [0, NC/2]
+#pragma unroll 1
+  for (int i = 0; i <= 8; ++i) {
+    const int k = t + NT * i;
+    if (k > NC / 2) break;
+    const int km = NC - k;
+    const cpx<T> W = twr[k];  // exp(-2 pi i k / N)
+    cpx<T> Yk, Ym;
+    if constexpr (SRC == 2) {
+      const float2 h0 = hsrc[k], h1 = hsrc[km];
+      Yk = {T(h0.x), T(h0.y)};
+      Ym = {T(h1.x), T(h1.y)};
+      if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
+    } else {
+      const int ia = lpad(k), ib = lpad(km & (NC - 1));
+      const cpx<T> A = {sre[ia], sim[ia]};
+      const cpx<T> Bm = {sre[ib], sim[ib]};
+      const cpx<T> s = cadd(A, cconj(Bm));
+      const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
+      cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
+      cpx<T> Xm = {T(0.5) * (s.x - u.y), T(0.5) * (-s.y - u.x)};
+      if constexpr (SRC == 1) {
+        Xk = cadd(Xk, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, k));
+        if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, km));
+      }
+      Yk = cscale(Xk, whiten_gain<T>(a, psd, k, NC, flag));
+      Ym = cscale(Xm, whiten_gain<T>(a, psd, km, NC, flag));
+      if (km == k) Ym = Yk;
+    }
+    // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
+    const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
+    const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
+    const int ia = lpad(k);
+    sre[ia] = p.x - q.y;
+    sim[ia] = p.y + q.x;
+    if (k != 0 && km != k) {
+      const int ib = lpad(km);
+      sre[ib] = p.x + q.y;
+      sim[ib] = -p.y + q.x;
+    }
+  }
+  __syncthreads();
+  block_fft<T, NC, +1, true>(v, sre, sim, t, tw);
+  float* o = a.out + bd * N;
+  const T sc = T(1) / T(NC);
+  const float* nz = nullptr;
+  if constexpr (SRC == 2) nz = a.bg + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int n = fft_out_index<NC>(t, e);
+    float2 y = {float(v[e].x * sc), float(v[e].y * sc)};
+    if constexpr (SRC == 2) {
+      y.x += nz[2 * n];
+      y.y += nz[2 * n + 1];
+    }
+    reinterpret_cast<float2*>(o)[n] = y;
+  }
+  if (flag) atomicOr(&sflag, flag);
+  __syncthreads();
+  if (t == 0 && sflag && a.status) atomicOr(a.status + b, sflag);
+}
+
+// ------------------------------------------------------------------ Welch
+struct WelchArgs {
+  DevCfg cf;
+  const float* bg;
+  int64_t L_bg;
+  const int64_t* offset;
+  float* psd;
+  const void* tw;  // cpx<T>[L], exp(-2 pi i n / L)
+  double norm;     // 1 / (K fs sum w^2)
+};
+
+// Twiddles of passes 1.. kept in registers for the whole segment loop.
+template <class T, int NC> struct RegTwiddle {
+  cpx<T> p[FftPlan<NC>::NPASS][16];
+  __device__ __forceinline__ void init(const cpx<T>* __restrict__ tab, int t) {
+    init_pass<1>(tab, t);
+    init_pass<2>(tab, t);
+    if constexpr (FftPlan<NC>::NPASS == 4) init_pass<3>(tab, t);
+  }
+  template <int PASS> __device__ __forceinline__ void init_pass(const cpx<T>* __restrict__ tab, int t) {
+    constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS, NT = NC / 16;
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+      const int k = (t + NT * m) & (NS - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[PASS][m * R + r] = tab[(r * k) * (NC / (NS * R))];
+    }
+  }
+  template <int PASS> __device__ __forceinline__ cpx<T> get(int m, int r, int) const {
+    return p[PASS][m * PassInfo<NC, PASS>::R + r];
+  }
+};
+
+// Per (sample, detector): K periodic-Hann segments of L samples at stride L/2
+// from [o, o + P).  Segments 2p and 2p+1 go through ONE complex FFT as real
+// and imaginary parts; since |A_k|^2 + |B_k|^2 = (|X_k|^2 + |X_{L-k}|^2)/2
+// for X = FFT(a + i b), the accumulated |X|^2 is folded once at the end.
+template <class T, class ACC, int NC>
+__global__ __launch_bounds__(NC / 16) void k_welch(WelchArgs a) {
+  constexpr int NT = NC / 16;
+  constexpr int LS = LdsSize<NC>::value;
+  static_assert(NC * sizeof(ACC) <= 2 * LS * sizeof(T), "fold buffer must fit in the FFT buffer");
+  __shared__ T lds[2 * LS];
+  T* sre = lds;
+  T* sim = lds + LS;
+  const int t = threadIdx.x;
+  const int64_t bd = blockIdx.x;
+  const int D = a.cf.n_det;
+  const int64_t b = bd / D;
+  const int d = int(bd - b * D);
+  const float* x = a.bg + int64_t(d) * a.L_bg + a.offset[b];
+  T w[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const T sp = sinpi_t(T(t + NT * r) / T(NC));
+    w[r] = sp * sp;
+  }
+  RegTwiddle<T, NC> tw;
+  tw.init(reinterpret_cast<const cpx<T>*>(a.tw), t);
+  ACC acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = ACC(0);
+  float carry[8];
+  const int K = a.cf.K;
+  const int npairs = (K + 1) / 2;
+#pragma unroll 1
+  for (int p = 0; p < npairs; ++p) {
+    const float* xp = x + int64_t(p) * NC;
+    float ra[16], rb[16];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) ra[r] = (p == 0) ? xp[t + NT * r] : carry[r];
+#pragma unroll
+    for (int r = 8; r < 16; ++r) ra[r] = xp[t + NT * r];
+    const bool has_b = (2 * p + 1) < K;
+    if (has_b) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) rb[r] = ra[r + 8];
+#pragma unroll
+      for (int r = 8; r < 16; ++r) rb[r] = xp[NC / 2 + t + NT * r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) rb[r] = 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) carry[r] = rb[r + 8];
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = {w[r] * T(ra[r]), w[r] * T(rb[r])};
+    if (p > 0) __syncthreads();
+    block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
+  }
+  __syncthreads();
+  ACC* fold = reinterpret_cast<ACC*>(lds);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC>(t, e)] = acc[e];
+  __syncthreads();
+  float* out = a.psd + bd * a.cf.Fw;
+  for (int k = t; k <= NC / 2; k += NT) {
+    const ACC s = (fold[k] + fold[(NC - k) & (NC - 1)]) * ACC(0.5);
+    const ACC ck = (k == 0 || k == NC / 2) ? ACC(1) : ACC(2);
+    out[k] = float(s * ck * ACC(a.norm));
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// ======================================================================= host
+
+struct gw_ctx {
+  gw_config cfg;
+  DevCfg dc;
+  double* kcbrt = nullptr;    // [F]  k^(1/3)
+  double* lnk3 = nullptr;     // [F]  ln(k)/3
+  void* tw_win = nullptr;     // cpx<T>[N/2]
+  void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
+  void* tw_welch = nullptr;   // cpx<T>[L]
+  std::string err;
+};
+
+namespace {
+
+const char* const kDetNames[3] = {"H1", "L1", "V1"};
+// geodetic latitude [deg N], longitude [deg E], x-arm and y-arm azimuth [deg
+// from North toward East]: public site survey values
+const double kSites[3][4] = {
+    {46.45514, -119.40766, 324.0000, 234.0000},
+    {30.56289, -90.77424, 252.2835, 162.2835},
+    {43.63141, 10.50450, 19.4326, 289.4326},
+};
+
+DetGeom make_detector(int id) {
+  const double deg = M_PI / 180.0;
+  const double lat = kSites[id][0] * deg, lon = kSites[id][1] * deg;
+  const double a = 6378137.0, f = 1.0 / 298.257223563, e2 = f * (2.0 - f);
+  const double nu = a / std::sqrt(1.0 - e2 * std::sin(lat) * std::sin(lat));
+  DetGeom g;
+  g.r[0] = nu * std::cos(lat) * std::cos(lon);
+  g.r[1] = nu * std::cos(lat) * std::sin(lon);
+  g.r[2] = nu * (1.0 - e2) * std::sin(lat);
+  const double east[3] = {-std::sin(lon), std::cos(lon), 0.0};
+  const double north[3] = {-std::sin(lat) * std::cos(lon), -std::sin(lat) * std::sin(lon), std::cos(lat)};
+  double x[3], y[3];
+  const double zx = kSites[id][2] * deg, zy = kSites[id][3] * deg;
+  for (int i = 0; i < 3; ++i) {
+    x[i] = std::cos(zx) * north[i] + std::sin(zx) * east[i];
+    y[i] = std::cos(zy) * north[i] + std::sin(zy) * east[i];
+  }
+  const int ij[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  for (int m = 0; m < 6; ++m) {
+    const int i = ij[m][0], j = ij[m][1];
+    g.D[m] = 0.5 * (x[i] * x[j] - y[i] * y[j]);
+  }
+  return g;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+gw_status fail(gw_ctx* c, gw_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+gw_status check_launch(gw_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, GW_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GW_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+template <class T>
+gw_status upload_twiddles(gw_ctx* c, void** dst, int n, int denom) {
+  std::vector<cpx<T>> h(n);
+  for (int i = 0; i < n; ++i) {
+    const double ang = -2.0 * M_PI * double(i) / double(denom);
+    h[i] = {T(std::cos(ang)), T(std::sin(ang))};
+  }
+  if (hipMalloc(dst, sizeof(cpx<T>) * n) != hipSuccess) return fail(c, GW_ENOMEM, "hipMalloc twiddles");
+  if (hipMemcpy(*dst, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, GW_EHIP, "hipMemcpy twiddles");
+  return GW_OK;
+}
+
+gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
+  auto bad = [&](const char* m) { *why = m; return GW_EINVAL; };
+  if (!g) return bad("config is NULL");
+  if (g->n_det < 1 || g->n_det > GW_MAX_DET) return bad("n_det must be in 1..4");
+  for (int d = 0; d < g->n_det; ++d)
+    if (g->det_id[d] < 0 || g->det_id[d] > 2) return bad("det_id must be 0 (H1), 1 (L1) or 2 (V1)");
+  if (!(g->fs > 0) || !(g->t_window > 0) || !(g->psd_length > 0) || !(g->fftlen > 0))
+    return bad("fs, t_window, psd_length, fftlen must be positive");
+  const double Nd = g->t_window * g->fs, Pd = g->psd_length * g->fs, Ld = g->fftlen * g->fs;
+  const double Sd = (g->fftlen - g->overlap) * g->fs;
+  auto integral = [](double v) { return std::fabs(v - std::round(v)) < 1e-9 && v < 1e12; };
+  if (!integral(Nd) || !integral(Pd) || !integral(Ld) || !integral(Sd))
+    return bad("t_window, psd_length, fftlen and overlap must be whole numbers of samples");
+  const int64_t N = std::llround(Nd), P = std::llround(Pd), L = std::llround(Ld), S = std::llround(Sd);
+  if (!is_pow2(N) || N < 2048 || N > 32768) return bad("N = t_window*fs must be a power of two in [2048, 32768]");
+  if (!is_pow2(L) || L < 2048 || L > 4096) return bad("L = fftlen*fs must be 2048 or 4096");
+  if (S * 2 != L) return bad("overlap must be half of fftlen (stride L/2)");
+  if (P < L || (P - L) % S) return bad("psd_length*fs - L must be a non-negative multiple of the stride");
+  if (N % L) return bad("t_window must be a whole multiple of fftlen");
+  if (!(g->f_min >= 0) || !(g->f_min < 0.5 * g->fs)) return bad("f_min must be in [0, fs/2)");
+  if (g->approximant < 0 || g->approximant > 1) return bad("approximant must be 0 or 1");
+  if (g->precision < 0 || g->precision > 2) return bad("precision must be 0, 1 or 2");
+  if (!(g->mc[0] > 0) || !(g->mc[1] >= g->mc[0])) return bad("bad chirp-mass range");
+  if (!(g->q[0] > 0) || !(g->q[1] >= g->q[0]) || g->q[1] > 1) return bad("bad mass-ratio range (0 < q <= 1)");
+  if (!(g->chi[0] > -1) || !(g->chi[1] < 1) || !(g->chi[1] >= g->chi[0])) return bad("bad spin range (|chi| < 1)");
+  if (!(g->dl[0] > 0) || !(g->dl[1] >= g->dl[0])) return bad("bad distance range");
+  if (g->precision == 2 && N > 16384) return GW_EUNSUPPORTED;
+  DevCfg c;
+  std::memset(&c, 0, sizeof(c));
+  c.n_det = g->n_det;
+  c.N = int(N);
+  c.F = int(N / 2 + 1);
+  c.P = int(P);
+  c.L = int(L);
+  c.S = int(S);
+  c.K = int((P - L) / S + 1);
+  c.Fw = int(L / 2 + 1);
+  c.ratio = int(N / L);
+  c.approximant = g->approximant;
+  c.precision = g->precision;
+  c.fs = g->fs;
+  c.T = g->t_window;
+  c.invT = 1.0 / g->t_window;
+  c.f_min = g->f_min;
+  for (int i = 0; i < 2; ++i) {
+    c.mc[i] = g->mc[i];
+    c.q[i] = g->q[i];
+    c.chi[i] = g->chi[i];
+    c.dl[i] = g->dl[i];
+  }
+  // first bin with k/T >= f_min (k/T rounded as the binary64 grid is formed)
+  int k = int(std::ceil(g->f_min * g->t_window));
+  while (k > 0 && double(k - 1) / g->t_window >= g->f_min) --k;
+  while (double(k) / g->t_window < g->f_min) ++k;
+  c.kmin = k;
+  for (int d = 0; d < g->n_det; ++d) c.det[d] = make_detector(g->det_id[d]);
+  *dc = c;
+  return GW_OK;
+}
+
+static int64_t ws_params_bytes(int64_t B) { return ((B * 12 * 8 + 255) / 256) * 256; }
+static int64_t ws_offset_bytes(int64_t B) { return ((B * 8 + 255) / 256) * 256; }
+static int64_t ws_psd_bytes(const DevCfg& d, int64_t B) { return ((B * d.n_det * d.Fw * 4 + 255) / 256) * 256; }
+
+// dispatch a k_window instantiation on the window FFT size
+template <class T, class TP, bool FULL, int SRC>
+static void launch_window(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
+  const int NC = d.N / 2;
+  switch (NC) {
+    case 2048: hipLaunchKernelGGL((k_window<T, TP, FULL, 2048, SRC>), dim3(unsigned(blocks)), dim3(128), 0, stream, a); break;
+    case 4096: hipLaunchKernelGGL((k_window<T, TP, FULL, 4096, SRC>), dim3(unsigned(blocks)), dim3(256), 0, stream, a); break;
+    case 8192: hipLaunchKernelGGL((k_window<T, TP, FULL, 8192, SRC>), dim3(unsigned(blocks)), dim3(512), 0, stream, a); break;
+    default:
+      if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((k_window<T, TP, FULL, 16384, SRC>), dim3(unsigned(blocks)), dim3(1024), 0, stream, a);
+      break;
+  }
+}
+
+template <int SRC>
+static void launch_window_prec(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
+  if (d.precision == 0) launch_window<float, float, false, SRC>(d, blocks, a, stream);
+  else if (d.precision == 1) launch_window<float, double, false, SRC>(d, blocks, a, stream);
+  else launch_window<double, double, true, SRC>(d, blocks, a, stream);
+}
+
+static WinArgs win_args(gw_ctx* c) {
+  WinArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.cf = c->dc;
+  a.kcbrt = c->kcbrt;
+  a.lnk3 = c->lnk3;
+  a.tw = c->tw_win;
+  a.twr = c->twr_win;
+  return a;
+}
+
+template <class T, class ACC>
+static void launch_welch(const DevCfg& d, int64_t blocks, const WelchArgs& a, hipStream_t stream) {
+  if (d.L == 2048) hipLaunchKernelGGL((k_welch<T, ACC, 2048>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+  else hipLaunchKernelGGL((k_welch<T, ACC, 4096>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+}
+
+static gw_status welch_launch(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset, int64_t B,
+                              float* psd, hipStream_t stream) {
+  const DevCfg& d = c->dc;
+  WelchArgs a{d, bg, L_bg, offset, psd, c->tw_welch, 1.0 / (double(d.K) * d.fs * (3.0 * d.L / 8.0))};
+  const int64_t blocks = B * d.n_det;
+  if (d.precision == 0) launch_welch<float, float>(d, blocks, a, stream);
+  else if (d.precision == 1) launch_welch<float, double>(d, blocks, a, stream);
+  else launch_welch<double, double>(d, blocks, a, stream);
+  return check_launch(c, "k_welch");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gw_strerror(gw_status s) {
+  switch (s) {
+    case GW_OK: return "ok";
+    case GW_EINVAL: return "invalid argument";
+    case GW_ENOMEM: return "device allocation failed";
+    case GW_EHIP: return "HIP error";
+    case GW_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* gw_last_error(const gw_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+gw_status gw_destroy(gw_ctx* c) {
+  if (!c) return GW_OK;
+  (void)hipFree(c->kcbrt);
+  (void)hipFree(c->lnk3);
+  (void)hipFree(c->tw_win);
+  (void)hipFree(c->twr_win);
+  (void)hipFree(c->tw_welch);
+  delete c;
+  return GW_OK;
+}
+
+gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
+  if (!out) return GW_EINVAL;
+  *out = nullptr;
+  DevCfg dc;
+  std::string why;
+  gw_status s = validate_cfg(cfg, &dc, &why);
+  if (s != GW_OK) return s;
+  gw_ctx* c = new gw_ctx();
+  c->cfg = *cfg;
+  c->dc = dc;
+  std::vector<double> hc(dc.F), hl(dc.F);
+  for (int k = 0; k < dc.F; ++k) {
+    hc[k] = std::cbrt(double(k));
+    hl[k] = k > 0 ? std::log(double(k)) / 3.0 : 0.0;
+  }
+  if (hipMalloc(&c->kcbrt, sizeof(double) * dc.F) != hipSuccess ||
+      hipMalloc(&c->lnk3, sizeof(double) * dc.F) != hipSuccess) {
+    gw_destroy(c);
+    return GW_ENOMEM;
+  }
+  if (hipMemcpy(c->kcbrt, hc.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->lnk3, hl.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess) {
+    gw_destroy(c);
+    return GW_EHIP;
+  }
+  const int NC = dc.N / 2;
+  if (dc.precision == 2) {
+    s = upload_twiddles<double>(c, &c->tw_win, NC, NC);
+    if (s == GW_OK) s = upload_twiddles<double>(c, &c->twr_win, NC / 2 + 1, dc.N);
+    if (s == GW_OK) s = upload_twiddles<double>(c, &c->tw_welch, dc.L, dc.L);
+  } else {
+    s = upload_twiddles<float>(c, &c->tw_win, NC, NC);
+    if (s == GW_OK) s = upload_twiddles<float>(c, &c->twr_win, NC / 2 + 1, dc.N);
+    if (s == GW_OK) s = upload_twiddles<float>(c, &c->tw_welch, dc.L, dc.L);
+  }
+  if (s != GW_OK) {
+    gw_destroy(c);
+    return s;
+  }
+  *out = c;
+  return GW_OK;
+}
+
+gw_status gw_query(const gw_ctx* c, int32_t key, int64_t* value) {
+  if (!c || !value) return GW_EINVAL;
+  const DevCfg& d = c->dc;
+  switch (key) {
+    case GW_Q_N: *value = d.N; break;
+    case GW_Q_F: *value = d.F; break;
+    case GW_Q_P: *value = d.P; break;
+    case GW_Q_L: *value = d.L; break;
+    case GW_Q_K: *value = d.K; break;
+    case GW_Q_FW: *value = d.Fw; break;
+    case GW_Q_NDET: *value = d.n_det; break;
+    case GW_Q_NPARAMS: *value = GW_N_PARAMS; break;
+    default: return GW_EINVAL;
+  }
+  return GW_OK;
+}
+
+gw_status gw_workspace_size(const gw_ctx* c, int64_t B, int64_t* bytes) {
+  if (!c || !bytes || B < 0) return GW_EINVAL;
+  *bytes = ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B);
+  return GW_OK;
+}
+
+#define GW_CHECK_CTX(c) \
+  if (!(c)) return GW_EINVAL;
+
+gw_status sample_params(gw_ctx* c, uint64_t seed, uint64_t first_index, int64_t B, int64_t L_bg,
+                        double* params, int64_t* offset, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0) return fail(c, GW_EINVAL, "B < 0");
+  if (B == 0) return GW_OK;
+  if (!params || !offset) return fail(c, GW_EINVAL, "params/offset is NULL");
+  if (!aligned16(params) || !aligned16(offset)) return fail(c, GW_EINVAL, "params/offset not 16-byte aligned");
+  const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
+  if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
+  SampleArgs a{c->dc, seed, first_index, B, span, params, offset, nullptr, nullptr};
+  hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, a);
+  return check_launch(c, "k_sample_params");
+}
+
+gw_status gen_fd_waveform(gw_ctx* c, const double* params, int64_t B, float* hp, float* hc, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B > 65535) return fail(c, GW_EINVAL, "B must be in [0, 65535]");
+  if (B == 0) return GW_OK;
+  if (!params || !hp || !hc) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned16(params) || !aligned16(hp) || !aligned16(hc)) return fail(c, GW_EINVAL, "pointer not 16-byte aligned");
+  WaveArgs a{c->dc, params, B, c->kcbrt, c->lnk3, hp, hc};
+  dim3 grid(unsigned((c->dc.F + 255) / 256), unsigned(B));
+  if (c->dc.precision == 0) hipLaunchKernelGGL((k_gen_fd_waveform<float, false>), grid, dim3(256), 0, stream, a);
+  else if (c->dc.precision == 1) hipLaunchKernelGGL((k_gen_fd_waveform<double, false>), grid, dim3(256), 0, stream, a);
+  else hipLaunchKernelGGL((k_gen_fd_waveform<double, true>), grid, dim3(256), 0, stream, a);
+  return check_launch(c, "k_gen_fd_waveform");
+}
+
+gw_status project_detectors(gw_ctx* c, const double* params, const float* hp, const float* hc, int64_t B,
+                            float* hdet, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B > 65535) return fail(c, GW_EINVAL, "B must be in [0, 65535]");
+  if (B == 0) return GW_OK;
+  if (!params || !hp || !hc || !hdet) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned16(params) || !aligned16(hp) || !aligned16(hc) || !aligned16(hdet))
+    return fail(c, GW_EINVAL, "pointer not 16-byte aligned");
+  ProjArgs a{c->dc, params, B, hp, hc, hdet};
+  dim3 grid(unsigned((c->dc.F + 255) / 256), unsigned(B));
+  if (c->dc.precision == 0) hipLaunchKernelGGL((k_project<float>), grid, dim3(256), 0, stream, a);
+  else hipLaunchKernelGGL((k_project<double>), grid, dim3(256), 0, stream, a);
+  return check_launch(c, "k_project");
+}
+
+static const int64_t kMaxBlocks = int64_t(1) << 31;
+
+gw_status inject(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset, const float* hdet, int64_t B,
+                 float* strain, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!bg || !offset || !hdet || !strain) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(offset) || !aligned16(hdet) || !aligned16(strain))
+    return fail(c, GW_EINVAL, "misaligned pointer");
+  if (L_bg < int64_t(c->dc.P) + c->dc.N) return fail(c, GW_EINVAL, "L_bg < P + N");
+  WinArgs a = win_args(c);
+  a.src = hdet;
+  a.bg = bg;
+  a.L_bg = L_bg;
+  a.offset = offset;
+  a.out = strain;
+  launch_window_prec<2>(c->dc, B * c->dc.n_det, a, stream);
+  return check_launch(c, "k_window<inject>");
+}
+
+gw_status welch_psd(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset, int64_t B, float* psd,
+                    hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!bg || !offset || !psd) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(offset) || !aligned16(psd)) return fail(c, GW_EINVAL, "misaligned pointer");
+  if (L_bg < int64_t(c->dc.P) + c->dc.N) return fail(c, GW_EINVAL, "L_bg < P + N");
+  return welch_launch(c, bg, L_bg, offset, B, psd, stream);
+}
+
+gw_status whiten(gw_ctx* c, const float* strain, const float* psd, int64_t B, float* out, uint32_t* status,
+                 hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!strain || !psd || !out) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned16(strain) || !aligned16(psd) || !aligned16(out) || (status && !aligned4(status)))
+    return fail(c, GW_EINVAL, "misaligned pointer");
+  if (status) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, status, B, 0u);
+    gw_status s = check_launch(c, "k_fill_u32");
+    if (s != GW_OK) return s;
+  }
+  WinArgs a = win_args(c);
+  a.src = strain;
+  a.psd = psd;
+  a.out = out;
+  a.status = status;
+  launch_window_prec<0>(c->dc, B * c->dc.n_det, a, stream);
+  return check_launch(c, "k_window<whiten>");
+}
+
+gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, const float* bg,
+                            int64_t L_bg, float* out, float* params_f32, uint32_t* status, void* workspace,
+                            int64_t workspace_bytes, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!bg || !out || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(out) || !aligned16(workspace) || (params_f32 && !aligned16(params_f32)) ||
+      (status && !aligned4(status)))
+    return fail(c, GW_EINVAL, "misaligned pointer");
+  int64_t need = 0;
+  gw_workspace_size(c, B, &need);
+  if (workspace_bytes < need) return fail(c, GW_EINVAL, "workspace too small");
+  const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
+  if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
+  if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
+  char* ws = static_cast<char*>(workspace);
+  double* params = reinterpret_cast<double*>(ws);
+  int64_t* offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
+  float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
+  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status};
+  hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
+  gw_status s = check_launch(c, "k_sample_params");
+  if (s != GW_OK) return s;
+  s = welch_launch(c, bg, L_bg, offset, B, psd, stream);
+  if (s != GW_OK) return s;
+  WinArgs a = win_args(c);
+  a.src = bg;
+  a.L_bg = L_bg;
+  a.offset = offset;
+  a.params = params;
+  a.B = B;
+  a.psd = psd;
+  a.out = out;
+  a.status = status;
+  launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
+  return check_launch(c, "k_window<fused>");
+}
+
+}  // extern "C"
