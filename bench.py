@@ -100,13 +100,16 @@ def cpu_baseline(cfg, bg, seed, B, budget_s, workers):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--log2-bg", type=int, default=27)
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="after the timed region, copy a buffer of this size three times "
+                         "(calibrates HBM byte counters against a known transfer)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this generator has no cross-GPU step "
@@ -177,6 +180,16 @@ def main():
     welch_bytes = B * n_det * (z["P"] + z["Fw"]) * 4
     welch_gbs = welch_bytes / (welch_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_welch", "paper_scale_B%d" % B)
+
+    if args.copy_probe_gib > 0:
+        n = int(args.copy_probe_gib * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x %d bytes read + written" % (4 * n))
+        del src, dst
 
     # whole step, algorithmic bytes per sample: D (P + N) reads + D N writes
     step_bytes = B * n_det * ((z["P"] + z["N"]) + z["N"]) * 4
