@@ -165,6 +165,43 @@ template <class T, int NC> struct TableTwiddle {
   }
 };
 
+// Table form with fewer loads: per butterfly, W, W^2, W^4 and W^8 come from
+// the table and the other powers are products of at most three of them
+// (rounding error a few ulp).  Used where twiddle loads would otherwise
+// dominate the load count and register pressure.
+template <class T, int NC> struct PowTwiddle {
+  const cpx<T>* __restrict__ tw;
+  template <int PASS, int R> __device__ __forceinline__ void all(int k, cpx<T>* w) const {
+    constexpr int NS = PassInfo<NC, PASS>::NS;
+    constexpr int STEP = NC / (NS * R);
+    const int i1 = k * STEP;
+    w[1] = tw[i1];
+    if constexpr (R >= 4) {
+      w[2] = tw[2 * i1];
+      w[3] = cmul(w[2], w[1]);
+    }
+    if constexpr (R >= 8) {
+      w[4] = tw[4 * i1];
+      w[5] = cmul(w[4], w[1]);
+      w[6] = cmul(w[4], w[2]);
+      w[7] = cmul(w[6], w[1]);
+    }
+    if constexpr (R >= 16) {
+      w[8] = tw[8 * i1];
+      w[9] = cmul(w[8], w[1]);
+      w[10] = cmul(w[8], w[2]);
+      w[11] = cmul(w[10], w[1]);
+      w[12] = cmul(w[8], w[4]);
+      w[13] = cmul(w[12], w[1]);
+      w[14] = cmul(w[12], w[2]);
+      w[15] = cmul(w[14], w[1]);
+    }
+  }
+};
+
+template <class TW> struct TwiddleIsPow { static constexpr bool value = false; };
+template <class T, int NC> struct TwiddleIsPow<PowTwiddle<T, NC>> { static constexpr bool value = true; };
+
 // One Stockham pass.  READ: take input from LDS (else registers already hold
 // it).  WRITE: scatter the output to LDS (else it stays in registers in the
 // final layout).  A barrier separates this pass's LDS reads from its writes;
@@ -190,8 +227,15 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
     const int j = t + NT * m;
     if constexpr (NS > 1) {
       const int k = j & (NS - 1);
+      if constexpr (TwiddleIsPow<TW>::value) {
+        cpx<T> w[R];
+        tw.template all<PASS, R>(k, w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[m * R + r] = twmul<DIR>(v[m * R + r], tw.template get<PASS>(m, r, k));
+        for (int r = 1; r < R; ++r) v[m * R + r] = twmul<DIR>(v[m * R + r], w[r]);
+      } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[m * R + r] = twmul<DIR>(v[m * R + r], tw.template get<PASS>(m, r, k));
+      }
     }
     dftR<R, DIR>(v + m * R);
   }

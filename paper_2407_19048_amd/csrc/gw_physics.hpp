@@ -26,10 +26,29 @@ __device__ __forceinline__ double frac1(double x) { return x - floor(x); }
 
 // precision-generic math
 __device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+// sin and cos of 2 pi x for x already reduced to [0, 1): the hardware
+// sine/cosine take revolutions (max abs error 1.3e-7 measured on gfx950 over
+// [0, 1)); binary64 uses the library routine
+__device__ __forceinline__ void sincos_rev(float x, float* s, float* c) {
+  *s = __builtin_amdgcn_sinf(x);
+  *c = __builtin_amdgcn_cosf(x);
+}
+__device__ __forceinline__ void sincos_rev(double x, double* s, double* c) { sincospi(2.0 * x, s, c); }
 __device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
 __device__ __forceinline__ float sinpi_t(float x) { return sinpif(x); }
 __device__ __forceinline__ double sinpi_t(double x) { return sinpi(x); }
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+// reciprocals: binary32 hardware approximation (about 1 ulp); binary64
+// hardware seed refined by two Newton steps to full precision
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ float pow_t(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double pow_t(double x, double y) { return pow(x, y); }
@@ -47,8 +66,8 @@ struct DetGeom {
 };
 
 struct DevCfg {
-  int n_det, N, F, P, L, S, K, Fw, ratio, approximant, precision, kmin;
-  double fs, T, invT, f_min;
+  int n_det, N, F, P, L, S, K, Fw, ratio, log2_ratio, approximant, precision, kmin;
+  double fs, T, invT, f_min, inv_ratio;
   double mc[2], q[2], chi[2], dl[2];
   DetGeom det[4];
 };
@@ -220,7 +239,7 @@ __device__ __forceinline__ TP wf_phase_rev(const WfScalars& w, int k, double kcb
   if (k < w.kt) {
     const TP v = TP(w.v1) * TP(kcbrt);
     const TP lnv = TP(w.lnv1) + TP(lnk3);
-    const TP iv = TP(1) / v;
+    const TP iv = rcp_t(v);
     const TP iv2 = iv * iv;
     const TP iv5 = iv2 * iv2 * iv;
     const TP p = TP(w.a[0]) +
@@ -239,7 +258,7 @@ __device__ __forceinline__ TP wf_phase_rev(const WfScalars& w, int k, double kcb
 
 template <class TA>
 __device__ __forceinline__ TA wf_amplitude(const WfScalars& w, int k, double kcbrt, double invT) {
-  if (k < w.kt) return TA(w.A0T) / (TA(k) * sqrt_t(TA(kcbrt)));
+  if (k < w.kt) return TA(w.A0T) * rsqrt_t(TA(kcbrt)) * rcp_t(TA(k));
   const TA f = TA(double(k) * invT);
   if (k < w.krd) return TA(w.At) * pow_t(f / TA(w.ft), TA(-2.0) / TA(3.0));
   const TA d = f - TA(w.f_rd);

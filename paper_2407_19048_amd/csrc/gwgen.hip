@@ -36,6 +36,8 @@ struct SampleArgs {
   int64_t* offset;
   float* params_f32;
   uint32_t* status;
+  WfScalars* wf;     // [B] waveform constants for the fused kernel, or NULL
+  DetScalars* dsc;   // [B][D] antenna patterns and delays, or NULL
 };
 
 __global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
@@ -75,6 +77,13 @@ __global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
     const double f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
     a.status[i] = f_cut > 0.5 * c.fs ? GW_STATUS_CUT_AT_NYQUIST : 0u;
   }
+  if (a.wf) {
+    WfScalars w;
+    wf_setup(a.params, a.B, i, c, w);
+    a.wf[i] = w;
+    for (int d = 0; d < c.n_det; ++d)
+      a.dsc[i * c.n_det + d] = det_response(c.det[d], w.ra, w.dec, w.psi, w.tc);
+  }
 }
 
 // -------------------------------------------------------- plus / cross
@@ -103,7 +112,7 @@ __global__ __launch_bounds__(256) void k_gen_fd_waveform(WaveArgs a) {
     TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst);
     rev = frac1(rev);
     TP s, c;
-    sincospi_t(TP(2) * rev, &s, &c);
+    sincos_rev(rev, &s, &c);
     const TP A = wf_amplitude<TP>(w, k, kc, a.cf.invT);
     const TP cp = A * TP(0.5) * (TP(1) + TP(w.cosi) * TP(w.cosi));
     const TP cx = A * TP(w.cosi);
@@ -144,7 +153,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   for (int d = 0; d < D; ++d) {
     const TP rev = frac1(TP(k) * TP(ds[d].tau * a.cf.invT));
     float s, c;
-    sincospif(float(2 * rev), &s, &c);
+    sincos_rev(float(rev), &s, &c);
     const float fp = float(ds[d].fp), fx = float(ds[d].fx), fs = float(a.cf.fs);
     const float2 h = {fs * (fp * hp.x + fx * hc.x), fs * (fp * hp.y + fx * hc.y)};
     // h * e^{-i phi}
@@ -168,19 +177,20 @@ struct WinArgs {
   const double* lnk3;
   const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
   const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
+  const WfScalars* wf;    // [B] (SRC 1)
+  const DetScalars* dsc;  // [B][D] (SRC 1)
 };
 
 // Whitening factor for window bin k in [0, N/2]; sets status bits.
 template <class T>
 __device__ __forceinline__ T whiten_gain(const WinArgs& a, const float* psd, int k, int NC, uint32_t& flag) {
   if (k == 0 || k >= NC || k < a.cf.kmin) return T(0);
-  const int r = a.cf.ratio;
-  const int i = k / r;
-  const T tt = T(k - i * r) / T(r);
+  const int i = k >> a.cf.log2_ratio;
+  const T tt = T(k - (i << a.cf.log2_ratio)) * T(a.cf.inv_ratio);
   const T S = (T(1) - tt) * T(psd[i]) + tt * T(psd[i + 1]);
   if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
   if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
-  return T(1) / sqrt_t(T(a.cf.fs) * S * T(0.5));
+  return rsqrt_t(T(a.cf.fs) * S * T(0.5));
 }
 
 // Projected signal (DFT coefficients) at window bin k, generated in registers.
@@ -191,7 +201,7 @@ __device__ __forceinline__ cpx<T> signal_bin(const WinArgs& a, const WfScalars& 
   TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
   rev = frac1(rev);
   T s, c;
-  sincospi_t(T(2) * T(rev), &s, &c);
+  sincos_rev(T(rev), &s, &c);
   const T A = T(a.cf.fs) * wf_amplitude<T>(w, k, kc, a.cf.invT);
   // fs A (cpl - i cxx)(c - i s)
   return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
@@ -199,13 +209,14 @@ __device__ __forceinline__ cpx<T> signal_bin(const WinArgs& a, const WfScalars& 
 
 // SRC 0: whiten strain.  SRC 1: fused background + signal + whiten.
 // SRC 2: inject (out = bg window + irfft(hdet)); src is hdet [B][D][N/2+1].
+// Occupancy target: two workgroups per CU (VGPR budget 128 for 512 threads).
+template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
+
 template <class T, class TP, bool FULL, int NC, int SRC>
-__global__ __launch_bounds__(NC / 16) void k_window(WinArgs a) {
+__global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a) {
   constexpr int NT = NC / 16;
   constexpr int LS = LdsSize<NC>::value;
   __shared__ T lds[2 * LS];
-  __shared__ WfScalars wsh;
-  __shared__ DetScalars dsh;
   __shared__ uint32_t sflag;
   T* sre = lds;
   T* sim = lds + LS;
@@ -216,7 +227,7 @@ __global__ __launch_bounds__(NC / 16) void k_window(WinArgs a) {
   const int d = int(bd - b * D);
   const int N = 2 * NC;
   const cpx<T>* twr = reinterpret_cast<const cpx<T>*>(a.twr);
-  TableTwiddle<T, NC> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
+  PowTwiddle<T, NC> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
   cpx<T> v[16];
   uint32_t flag = 0;
   if (t == 0) sflag = 0;
@@ -225,14 +236,9 @@ __global__ __launch_bounds__(NC / 16) void k_window(WinArgs a) {
     const float* x = (SRC == 0) ? a.src + bd * N : a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int n = t + NT * r;
-      v[r] = {T(x[2 * n]), T(x[2 * n + 1])};
-    }
-    if constexpr (SRC == 1) {
-      if (t == 0) {
-        wf_setup(a.params, a.B, b, a.cf, wsh);
-        dsh = det_response(a.cf.det[d], wsh.ra, wsh.dec, wsh.psi, wsh.tc);
-      }
+      float2 q;
+      __builtin_memcpy(&q, x + 2 * (t + NT * r), sizeof(q));
+      v[r] = {T(q.x), T(q.y)};
     }
     block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
     __syncthreads();
@@ -248,7 +254,9 @@ __global__ __launch_bounds__(NC / 16) void k_window(WinArgs a) {
   const float* psd = a.psd + bd * a.cf.Fw;
   T cpl = T(0), cxx = T(0);
   double tauT = 0.0;
+  const WfScalars& wsh = a.wf[SRC == 1 ? b : 0];
   if constexpr (SRC == 1) {
+    const DetScalars dsh = a.dsc[bd];
     cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
     cxx = T(dsh.fx * wsh.cosi);
     tauT = dsh.tau * a.cf.invT;
@@ -379,32 +387,39 @@ __global__ __launch_bounds__(NC / 16) void k_welch(WelchArgs a) {
   ACC acc[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = ACC(0);
-  float carry[8];
+  // Pair p covers [p L, p L + 3L/2).  Its first half-segment was read by
+  // pair p-1; the next pair's 16 new values per thread are requested before
+  // the current transform so that their latency hides behind it.
   const int K = a.cf.K;
   const int npairs = (K + 1) / 2;
+  float cur[8], na[8], nb[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    cur[r] = x[t + NT * r];
+    na[r] = x[t + NT * (r + 8)];
+    nb[r] = (K > 1) ? x[NC / 2 + t + NT * (r + 8)] : 0.f;
+  }
 #pragma unroll 1
   for (int p = 0; p < npairs; ++p) {
-    const float* xp = x + int64_t(p) * NC;
-    float ra[16], rb[16];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) ra[r] = (p == 0) ? xp[t + NT * r] : carry[r];
-#pragma unroll
-    for (int r = 8; r < 16; ++r) ra[r] = xp[t + NT * r];
     const bool has_b = (2 * p + 1) < K;
-    if (has_b) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) rb[r] = ra[r + 8];
-#pragma unroll
-      for (int r = 8; r < 16; ++r) rb[r] = xp[NC / 2 + t + NT * r];
-    } else {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) rb[r] = 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) carry[r] = rb[r + 8];
     cpx<T> v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = {w[r] * T(ra[r]), w[r] * T(rb[r])};
+    for (int r = 0; r < 8; ++r) {
+      const float b_hi = has_b ? nb[r] : 0.f;
+      const float b_lo = has_b ? na[r] : 0.f;
+      v[r] = {w[r] * T(cur[r]), w[r] * T(b_lo)};
+      v[r + 8] = {w[r + 8] * T(na[r]), w[r + 8] * T(b_hi)};
+      cur[r] = nb[r];
+    }
+    if (p + 1 < npairs) {
+      const float* xn = x + int64_t(p + 1) * NC;
+      const bool nb_ok = (2 * (p + 1) + 1) < K;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        na[r] = xn[t + NT * (r + 8)];
+        nb[r] = nb_ok ? xn[NC / 2 + t + NT * (r + 8)] : 0.f;
+      }
+    }
     if (p > 0) __syncthreads();
     block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
 #pragma unroll
@@ -546,6 +561,9 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   c.K = int((P - L) / S + 1);
   c.Fw = int(L / 2 + 1);
   c.ratio = int(N / L);
+  c.log2_ratio = 0;
+  while ((1 << c.log2_ratio) < c.ratio) ++c.log2_ratio;
+  c.inv_ratio = 1.0 / double(c.ratio);
   c.approximant = g->approximant;
   c.precision = g->precision;
   c.fs = g->fs;
@@ -571,6 +589,8 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
 static int64_t ws_params_bytes(int64_t B) { return ((B * 12 * 8 + 255) / 256) * 256; }
 static int64_t ws_offset_bytes(int64_t B) { return ((B * 8 + 255) / 256) * 256; }
 static int64_t ws_psd_bytes(const DevCfg& d, int64_t B) { return ((B * d.n_det * d.Fw * 4 + 255) / 256) * 256; }
+static int64_t ws_wf_bytes(int64_t B) { return ((B * int64_t(sizeof(WfScalars)) + 255) / 256) * 256; }
+static int64_t ws_det_bytes(const DevCfg& d, int64_t B) { return ((B * d.n_det * int64_t(sizeof(DetScalars)) + 255) / 256) * 256; }
 
 // dispatch a k_window instantiation on the window FFT size
 template <class T, class TP, bool FULL, int SRC>
@@ -712,7 +732,7 @@ gw_status gw_query(const gw_ctx* c, int32_t key, int64_t* value) {
 
 gw_status gw_workspace_size(const gw_ctx* c, int64_t B, int64_t* bytes) {
   if (!c || !bytes || B < 0) return GW_EINVAL;
-  *bytes = ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B);
+  *bytes = ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B) + ws_wf_bytes(B) + ws_det_bytes(c->dc, B);
   return GW_OK;
 }
 
@@ -728,7 +748,7 @@ gw_status sample_params(gw_ctx* c, uint64_t seed, uint64_t first_index, int64_t 
   if (!aligned16(params) || !aligned16(offset)) return fail(c, GW_EINVAL, "params/offset not 16-byte aligned");
   const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
   if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
-  SampleArgs a{c->dc, seed, first_index, B, span, params, offset, nullptr, nullptr};
+  SampleArgs a{c->dc, seed, first_index, B, span, params, offset, nullptr, nullptr, nullptr, nullptr};
   hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, a);
   return check_launch(c, "k_sample_params");
 }
@@ -836,7 +856,9 @@ gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int6
   double* params = reinterpret_cast<double*>(ws);
   int64_t* offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
   float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
-  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status};
+  WfScalars* wf = reinterpret_cast<WfScalars*>(ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B));
+  DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
+  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status, wf, dsc};
   hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
   gw_status s = check_launch(c, "k_sample_params");
   if (s != GW_OK) return s;
@@ -851,6 +873,8 @@ gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int6
   a.psd = psd;
   a.out = out;
   a.status = status;
+  a.wf = wf;
+  a.dsc = dsc;
   launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
   return check_launch(c, "k_window<fused>");
 }
