@@ -198,6 +198,83 @@ gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
                             void* workspace, int64_t workspace_bytes,
                             hipStream_t stream);
 
+
+/* ------------------------------------------------------------------------
+ * Learned waveform surrogate (an addition of this library to the waveform
+ * step of section 3.1; approximant 1 only).  A 4-256-256-256-128 MLP with
+ * bfloat16 MFMA forward/backward kernels (binary32 accumulation, binary32
+ * master weights, AdamW) maps (M_c, q, chi1, chi2) to 64 + 64 reduced-basis
+ * coefficients of the amplitude ratio A/A_N and phase residual P - P_N on
+ * 1024 nodes log-spaced in geometric frequency Mf in [2e-3, 0.2].
+ * Coefficients = A^T phi(theta) + zstd * z + zmean, where phi holds the PN
+ * phase-coefficient functions (a least-squares skip path) and z is the MLP
+ * output.  Training data come from the plain IMR-form model of this library.
+ * A linear head on the last hidden layer predicts log10 of the mismatch; the
+ * fused surrogate batch falls back to the plain model where it exceeds a
+ * threshold.  The handle owns its weights and scratch for up to max_batch
+ * rows; all data buffers are caller-owned device memory unless noted.
+ * ------------------------------------------------------------------------ */
+typedef struct gw_surrogate gw_surrogate;
+#define GW_SURR_NODES 1024
+#define GW_SURR_OUT 128
+#define GW_SURR_FEAT 9
+#define GW_SURR_HIDDEN 256
+
+gw_status gw_surrogate_create(gw_ctx* ctx, int64_t max_batch, gw_surrogate** out);
+gw_status gw_surrogate_destroy(gw_surrogate* s);
+const char* gw_surrogate_last_error(const gw_surrogate* s);
+/* number of floats in the flat weight layout [W0 (16x256), b0, W1, b1, W2, b2,
+ * W3 (256x128), b3], W stored [in][out] row-major; input rows 4..15 of W0 are
+ * padding and stay zero */
+int64_t gw_surrogate_n_weights(void);
+gw_status gw_surrogate_set_weights(gw_surrogate* s, const float* host_flat, int64_t n);   /* host array; resets Adam */
+gw_status gw_surrogate_get_weights(gw_surrogate* s, float* host_flat, int64_t n);         /* host array */
+/* targets of the plain model at the nodes: ratio, dpsi float [B][1024];
+ * feat double [B][9] (phi) */
+gw_status gw_surrogate_targets(gw_surrogate* s, const double* params, int64_t B, float* ratio, float* dpsi,
+                               double* feat, hipStream_t stream);
+/* reduced basis (64 per target) from the first n target rows; synchronous */
+gw_status gw_surrogate_fit_basis(gw_surrogate* s, const float* ratio, const float* dpsi, int64_t n, hipStream_t stream);
+/* coefficients C float [n][128] (64 amplitude then 64 phase) */
+gw_status gw_surrogate_project(gw_surrogate* s, const float* ratio, const float* dpsi, int64_t n, float* C,
+                               hipStream_t stream);
+/* least-squares skip path and standardisation; Z float [n][128] receives the
+ * standardised residual targets; synchronous */
+gw_status gw_surrogate_fit_skip(gw_surrogate* s, const double* feat, const float* C, int64_t n, float* Z,
+                                hipStream_t stream);
+gw_status gw_surrogate_standardise(gw_surrogate* s, const double* feat, const float* C, int64_t n, float* Z,
+                                   hipStream_t stream);
+/* theta float [B][4] = (M_c, q, chi1, chi2); out/z float [B][128] */
+gw_status gw_surrogate_forward(gw_surrogate* s, const float* theta, int64_t B, float* out, hipStream_t stream);
+/* gradients of the mean-squared loss (flat layout, device float) and the
+ * summed squared error (device float[1] or NULL); no update */
+gw_status gw_surrogate_gradients(gw_surrogate* s, const float* theta, const float* z, int64_t B, float* grads,
+                                 float* loss, hipStream_t stream);
+/* one AdamW step (beta 0.9/0.999, eps 1e-8) on a batch of B <= max_batch */
+gw_status gw_surrogate_train_step(gw_surrogate* s, const float* theta, const float* z, int64_t B, float lr,
+                                  float weight_decay, float* loss, hipStream_t stream);
+/* last hidden layer float [B][256] */
+gw_status gw_surrogate_hidden(gw_surrogate* s, const float* theta, int64_t B, float* h3, hipStream_t stream);
+gw_status gw_surrogate_set_head(gw_surrogate* s, const float* host_head, int64_t n);      /* 257 floats */
+/* ridge fit of the log10-mismatch head on h3 (device) and y (host); synchronous */
+gw_status gw_surrogate_fit_head(gw_surrogate* s, const float* h3, const float* y_host, int64_t n, double ridge);
+/* node values float [B][2][1024] and predicted log10 mismatch float [B] (or NULL) */
+gw_status gw_surrogate_nodes(gw_surrogate* s, const double* params, int64_t B, float* nodes, float* logmm,
+                             hipStream_t stream);
+/* h+, hx (interleaved complex float [B][N/2+1]) from node values; same
+ * conventions and band as gen_fd_waveform */
+gw_status gw_surrogate_waveform(gw_surrogate* s, const double* params, const float* nodes, int64_t B, float* hp,
+                                float* hc, hipStream_t stream);
+/* noise-weighted mismatch 1 - <a|b>/sqrt(<a|a><b|b>), <a|b> = 4 df Re sum
+ * a conj(b)/S over f_min <= f_k < f_cut (IMR-form cut from params, or all
+ * bins below Nyquist if params is NULL), 0 < k < N/2.  ha, hb interleaved
+ * complex float [B][N/2+1]; psd float [N/2+1]; mm double [B]. */
+gw_status gw_mismatch(gw_ctx* ctx, const float* ha, const float* hb, const float* psd, const double* params,
+                      int64_t B, double* mm, hipStream_t stream);
+/* host file with basis, skip path, standardisation, head and weights */
+gw_status gw_surrogate_save(gw_surrogate* s, const char* path);
+gw_status gw_surrogate_load(gw_surrogate* s, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

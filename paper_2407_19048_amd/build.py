@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(_HERE, "csrc", "gwgen.hip")
+SRCS = [os.path.join(_HERE, "csrc", n) for n in ("gwgen.hip", "gw_surrogate.hip")]
 OUT = os.path.join(_HERE, "libgwgen.so")
 
 HIPCC_FLAGS = [
@@ -21,7 +21,7 @@ HIPCC_FLAGS = [
 def build(verbose=True):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp, SRC]
+    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

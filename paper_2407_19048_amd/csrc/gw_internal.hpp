@@ -1,0 +1,24 @@
+// Host-side definitions shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "gw_physics.hpp"
+#include "../../include/gwgen.h"
+
+struct gw_ctx {
+  gw_config cfg;
+  gw::DevCfg dc;
+  double* kcbrt = nullptr;    // [F]  k^(1/3)
+  double* lnk3 = nullptr;     // [F]  ln(k)/3
+  void* tw_win = nullptr;     // cpx<T>[N/2]
+  void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
+  void* tw_welch = nullptr;   // cpx<T>[L]
+  std::string err;
+};
+
+namespace gw {
+gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg);
+gw_status ctx_check_launch(gw_ctx* c, const char* what);
+}  // namespace gw

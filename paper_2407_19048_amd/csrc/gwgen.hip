@@ -21,6 +21,7 @@
 
 #include "gw_fft.hpp"
 #include "gw_physics.hpp"
+#include "gw_internal.hpp"
 #include "../../include/gwgen.h"
 
 using namespace gw;
@@ -447,17 +448,6 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 
 // ======================================================================= host
 
-struct gw_ctx {
-  gw_config cfg;
-  DevCfg dc;
-  double* kcbrt = nullptr;    // [F]  k^(1/3)
-  double* lnk3 = nullptr;     // [F]  ln(k)/3
-  void* tw_win = nullptr;     // cpx<T>[N/2]
-  void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
-  void* tw_welch = nullptr;   // cpx<T>[L]
-  std::string err;
-};
-
 namespace {
 
 const char* const kDetNames[3] = {"H1", "L1", "V1"};
@@ -506,6 +496,15 @@ gw_status check_launch(gw_ctx* c, const char* what) {
   if (e != hipSuccess) return fail(c, GW_EHIP, std::string(what) + ": " + hipGetErrorString(e));
   return GW_OK;
 }
+
+}  // namespace
+
+namespace gw {
+gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg) { return fail(c, s, msg); }
+gw_status ctx_check_launch(gw_ctx* c, const char* what) { return check_launch(c, what); }
+}  // namespace gw
+
+namespace {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }

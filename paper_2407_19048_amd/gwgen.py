@@ -23,7 +23,14 @@ N_PARAMS = 12
 # names declared in include/gwgen.h
 EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query",
            "gw_workspace_size", "sample_params", "gen_fd_waveform", "project_detectors",
-           "inject", "welch_psd", "whiten", "gw_generate_batch")
+           "inject", "welch_psd", "whiten", "gw_generate_batch",
+           "gw_surrogate_create", "gw_surrogate_destroy", "gw_surrogate_last_error",
+           "gw_surrogate_n_weights", "gw_surrogate_set_weights", "gw_surrogate_get_weights",
+           "gw_surrogate_targets", "gw_surrogate_fit_basis", "gw_surrogate_project",
+           "gw_surrogate_fit_skip", "gw_surrogate_standardise", "gw_surrogate_forward",
+           "gw_surrogate_gradients", "gw_surrogate_train_step", "gw_surrogate_hidden",
+           "gw_surrogate_set_head", "gw_surrogate_fit_head", "gw_surrogate_nodes",
+           "gw_surrogate_waveform", "gw_mismatch", "gw_surrogate_save", "gw_surrogate_load")
 
 
 class GWConfig(ctypes.Structure):
@@ -62,6 +69,28 @@ def lib():
             "welch_psd": ([vp, vp, i64, vp, i64, vp, vp], i32),
             "whiten": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "gw_generate_batch": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp, i64, vp], i32),
+            "gw_surrogate_create": ([vp, i64, ctypes.POINTER(vp)], i32),
+            "gw_surrogate_destroy": ([vp], i32),
+            "gw_surrogate_last_error": ([vp], ctypes.c_char_p),
+            "gw_surrogate_n_weights": ([], i64),
+            "gw_surrogate_set_weights": ([vp, vp, i64], i32),
+            "gw_surrogate_get_weights": ([vp, vp, i64], i32),
+            "gw_surrogate_targets": ([vp, vp, i64, vp, vp, vp, vp], i32),
+            "gw_surrogate_fit_basis": ([vp, vp, vp, i64, vp], i32),
+            "gw_surrogate_project": ([vp, vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_fit_skip": ([vp, vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_standardise": ([vp, vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_forward": ([vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_gradients": ([vp, vp, vp, i64, vp, vp, vp], i32),
+            "gw_surrogate_train_step": ([vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, vp, vp], i32),
+            "gw_surrogate_hidden": ([vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_set_head": ([vp, vp, i64], i32),
+            "gw_surrogate_fit_head": ([vp, vp, vp, i64, ctypes.c_double], i32),
+            "gw_surrogate_nodes": ([vp, vp, i64, vp, vp, vp], i32),
+            "gw_surrogate_waveform": ([vp, vp, vp, i64, vp, vp, vp], i32),
+            "gw_mismatch": ([vp, vp, vp, vp, vp, i64, vp, vp], i32),
+            "gw_surrogate_save": ([vp, ctypes.c_char_p], i32),
+            "gw_surrogate_load": ([vp, ctypes.c_char_p], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -222,6 +251,17 @@ class Generator:
                                             bg.shape[1], _ptr(out), _ptr(params_f32), _ptr(status),
                                             _ptr(workspace), nbytes, _stream()),
                     "gw_generate_batch")
+
+    def mismatch(self, ha, hb, psd, params, mm):
+        """Noise-weighted mismatch per sample (see gw_mismatch)."""
+        import torch
+        B = ha.shape[0]
+        _want(ha, torch.complex64, (B, self.sizes["F"]), "ha")
+        _want(hb, torch.complex64, (B, self.sizes["F"]), "hb")
+        _want(psd, torch.float32, (self.sizes["F"],), "psd")
+        _want(mm, torch.float64, (B,), "mm")
+        self._check(lib().gw_mismatch(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
+                                      _stream()), "gw_mismatch")
 
     def workspace_views(self, workspace, B):
         """(params float64 [12][B], offsets int64 [B]) inside a batch workspace."""
