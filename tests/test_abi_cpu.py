@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     txt = open(os.path.join(ROOT, "include", "gwgen.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:gw_status|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:gw_status|const char\*|int64_t)\s+(\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_header_declares_the_six_steps_and_batch():
