@@ -95,6 +95,92 @@ def cpu_baseline(cfg, bg, seed, B, budget_s, workers):
                        "with start-up" % (done, n_distinct, busy, workers, wall))
 
 
+# --------------------------------------------------------- surrogate leg
+
+def surrogate_leg(gen, bg, args, K, W, dev):
+    """Learned-surrogate path at batch 8192: train it on the GPU (setup, not
+    timed), measure held-out mismatch against the plain model, then time the
+    fused surrogate batch and the plain batch at the same size."""
+    import numpy as np
+    import torch
+    from paper_2407_19048_amd import inputs
+    from paper_2407_19048_amd import surrogate as GS
+    B = args.surrogate_batch
+    z = gen.sizes
+    f = np.arange(z["F"]) / gen.cfg["t_window"]
+    psd = torch.from_numpy(inputs.true_psd(f, gen.cfg["fs"]).astype(np.float32)).to(dev)
+    t0 = time.perf_counter()
+    s = GS.Surrogate(gen, max_batch=8192)
+    fit = s.fit(seed=3, n_basis=16384, n_train=1 << 19, epochs=40, batch=8192, lr=2e-3, n_head=8192, psd=psd)
+    t_fit = time.perf_counter() - t0
+    log("surrogate trained in %.1f s (final mse %.3f)" % (t_fit, fit["final_mse"]))
+    # held-out mismatch
+    p = torch.empty((12, 8192), dtype=torch.float64, device=dev)
+    o = torch.empty(8192, dtype=torch.int64, device=dev)
+    gen.sample_params(4, 1 << 41, 8192, z["P"] + z["N"], p, o)
+    mm, logmm = s.mismatch_vs_plain(p, psd)
+    mm = mm.cpu().numpy()
+    fb = (logmm.cpu().numpy() > -3.0)
+    # waveform stage alone, same draws
+    hp = torch.empty((8192, z["F"]), dtype=torch.complex64, device=dev)
+    hc = torch.empty_like(hp)
+    nodes = torch.empty((8192, 2, 1024), dtype=torch.float32, device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    gen.gen_fd_waveform(p, hp, hc)
+    s.nodes(p, nodes)
+    s.waveform(p, nodes, hp, hc)
+    e[0].record()
+    for _ in range(5):
+        gen.gen_fd_waveform(p, hp, hc)
+    e[1].record()
+    for _ in range(5):
+        s.nodes(p, nodes)
+        s.waveform(p, nodes, hp, hc)
+    e[2].record()
+    torch.cuda.synchronize()
+    wf_plain, wf_surr = e[0].elapsed_time(e[1]) / 5, e[1].elapsed_time(e[2]) / 5
+    del hp, hc, nodes
+    # whole batch, surrogate vs plain at B
+    out = torch.empty((B, z["D"], z["N"]), dtype=torch.float32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    ws_s = gen.alloc_workspace_surrogate(B, device=dev)
+    ws_p = gen.alloc_workspace(B, device=dev)
+    timing = {}
+    fallback_rate = 0.0
+    for name in ("surrogate", "plain"):
+        for i in range(W):
+            if name == "surrogate":
+                gen.generate_batch_surrogate(s, 5, i, B, bg, out, ws_s, status=status)
+            else:
+                gen.generate_batch(5, i, B, bg, out, ws_p, status=status)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(K):
+            if name == "surrogate":
+                gen.generate_batch_surrogate(s, 5, W + i, B, bg, out, ws_s, status=status)
+            else:
+                gen.generate_batch(5, W + i, B, bg, out, ws_p, status=status)
+        torch.cuda.synchronize()
+        timing[name] = (time.perf_counter() - t1) / K
+        if name == "surrogate":
+            fallback_rate = float(((status.cpu().numpy() & 16) != 0).mean())
+    del out, ws_s, ws_p
+    return {
+        "batch": B,
+        "value": round(B / timing["surrogate"], 1),
+        "plain_value_same_batch": round(B / timing["plain"], 1),
+        "end_to_end_gain": round(timing["plain"] / timing["surrogate"], 4),
+        "ms_per_step": round(1e3 * timing["surrogate"], 4),
+        "waveform_stage_ms": {"plain": round(wf_plain, 4), "surrogate": round(wf_surr, 4),
+                              "gain": round(wf_plain / wf_surr, 3)},
+        "mismatch_heldout": {"n": 8192, "median": float(np.median(mm)), "p90": float(np.percentile(mm, 90)),
+                             "median_after_fallback": float(np.median(np.where(fb, 0.0, mm)))},
+        "fallback_rate": round(fallback_rate, 4),
+        "train_seconds": round(t_fit, 2),
+        "train_steps": fit["steps"],
+    }
+
+
 # ------------------------------------------------------------------- main
 
 def main():
@@ -107,6 +193,8 @@ def main():
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-batch", type=int, default=8192)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy a buffer of this size three times "
                          "(calibrates HBM byte counters against a known transfer)")
@@ -197,6 +285,10 @@ def main():
     log("step %.3f ms (%.0f GB/s algorithmic, %.1f %% of HBM peak); welch %.3f ms (%.0f GB/s)"
         % (ms_step, step_gbs, 100 * step_gbs / HBM_PEAK_GBS, welch_ms, welch_gbs))
 
+    surrogate = None
+    if not args.no_surrogate:
+        surrogate = surrogate_leg(gen, bg, args, K, W, dev)
+
     rec = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -229,6 +321,7 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        "surrogate": surrogate,
     }
     print(json.dumps(rec), flush=True)
 

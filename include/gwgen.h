@@ -56,6 +56,7 @@ typedef int32_t gw_status;
 #define GW_STATUS_NONPOSITIVE_PSD 2u /* a kept PSD bin was <= 0                */
 #define GW_STATUS_NONFINITE_DATA 4u  /* a window value was NaN/Inf             */
 #define GW_STATUS_CUT_AT_NYQUIST 8u  /* waveform cut-off above fs/2            */
+#define GW_STATUS_SURROGATE_FALLBACK 16u /* surrogate batch: plain model used  */
 
 #define GW_N_PARAMS 12
 #define GW_MAX_DET 4
@@ -87,6 +88,7 @@ typedef struct gw_config {
 } gw_config;
 
 typedef struct gw_ctx gw_ctx;
+typedef struct gw_surrogate gw_surrogate;
 
 /* Create a context: validate the configuration, build detector geometry and
  * twiddle/power tables on the current HIP device.  Allocates device memory
@@ -214,7 +216,6 @@ gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
  * threshold.  The handle owns its weights and scratch for up to max_batch
  * rows; all data buffers are caller-owned device memory unless noted.
  * ------------------------------------------------------------------------ */
-typedef struct gw_surrogate gw_surrogate;
 #define GW_SURR_NODES 1024
 #define GW_SURR_OUT 128
 #define GW_SURR_FEAT 9
@@ -271,6 +272,24 @@ gw_status gw_surrogate_waveform(gw_surrogate* s, const double* params, const flo
  * complex float [B][N/2+1]; psd float [N/2+1]; mm double [B]. */
 gw_status gw_mismatch(gw_ctx* ctx, const float* ha, const float* hb, const float* psd, const double* params,
                       int64_t B, double* mm, hipStream_t stream);
+/* Bytes of workspace gw_generate_batch_surrogate needs for batch size B. */
+gw_status gw_workspace_size_surrogate(const gw_ctx* ctx, int64_t B, int64_t* bytes);
+/* gw_generate_batch with the waveform taken from the surrogate: prior draws,
+ * surrogate node values and predicted log10 mismatch, Welch PSDs, then the
+ * fused window kernel building each bin's signal from the node values
+ * (binary64 Newtonian phase + interpolated residual).  Samples whose predicted
+ * log10 mismatch exceeds log10_mm_max use the plain model instead and get
+ * GW_STATUS_SURROGATE_FALLBACK.  Workspace: gw_workspace_size_surrogate(B)
+ * bytes, laid out as for gw_generate_batch followed by the node values. */
+gw_status gw_generate_batch_surrogate(gw_ctx* ctx, gw_surrogate* s, uint64_t seed, uint64_t batch_index,
+                                      int64_t B, const float* bg, int64_t L_bg, float* out, float* params_f32,
+                                      uint32_t* status, float log10_mm_max, void* workspace,
+                                      int64_t workspace_bytes, hipStream_t stream);
+/* Set the non-network state from host arrays: basis float [2][64][1024],
+ * mean double [2][1024], skip path A float [9][128], zmean/zstd float [128],
+ * head float [257] (weights: gw_surrogate_set_weights). */
+gw_status gw_surrogate_set_state(gw_surrogate* s, const float* basis, const double* mean, const float* A,
+                                 const float* zmean, const float* zstd, const float* head);
 /* host file with basis, skip path, standardisation, head and weights */
 gw_status gw_surrogate_save(gw_surrogate* s, const char* path);
 gw_status gw_surrogate_load(gw_surrogate* s, const char* path);

@@ -146,6 +146,26 @@ def interp_nodes(values, Ms, f):
     return (1.0 - t) * values[i] + t * values[i + 1]
 
 
+def nodes_from_state(theta, feat, weights, A, zmean, zstd, basis, mean, lo, hi):
+    """Node values [B][2][NN] from the surrogate state: coefficients
+    phi A + zstd z + zmean with z the MLP output, then mean + coef V."""
+    x = normalise_inputs(theta, lo, hi)
+    z, _ = mlp_forward(weights, x, emulate_bf16=True)
+    coef = feat @ A + zstd * z + zmean
+    ratio = mean[0] + coef[:, :N_BASIS] @ basis[0]
+    dpsi = mean[1] + coef[:, N_BASIS:] @ basis[1]
+    return np.stack([ratio, dpsi], axis=1)
+
+
+def reconstruct(cfg, p, ratio_nodes, dpsi_nodes):
+    """(h+, hx) on the window grid from node values."""
+    hp = reconstruct_hp(cfg, p, ratio_nodes, dpsi_nodes)
+    ci = math.cos(p[5])
+    c2 = 0.5 * (1.0 + ci * ci)
+    hc = np.where(np.abs(hp) > 0, -1j * hp * (ci / c2), 0.0) if c2 != 0 else np.zeros_like(hp)
+    return hp, hc
+
+
 def reconstruct_hp(cfg, p, ratio_nodes, dpsi_nodes):
     """h+ on the window grid from node values (iota, D_L, phi_c from p)."""
     from .pipeline import fd_grid

@@ -101,28 +101,28 @@ struct WaveArgs {
 template <class TP, bool FULL>
 __global__ __launch_bounds__(256) void k_gen_fd_waveform(WaveArgs a) {
   __shared__ WfScalars w;
-  const int64_t b = blockIdx.y;
+  const int64_t b = blockIdx.x;
   if (threadIdx.x == 0) wf_setup(a.params, a.B, b, a.cf, w);
   __syncthreads();
-  const int k = blockIdx.x * 256 + threadIdx.x;
   const int F = a.cf.F;
-  if (k >= F) return;
-  float2 hp = {0.f, 0.f}, hc = {0.f, 0.f};
-  if (k > 0 && k >= a.cf.kmin && k < w.kend) {
-    const double kc = a.kcbrt[k], lk = a.lnk3[k];
-    TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst);
-    rev = frac1(rev);
-    TP s, c;
-    sincos_rev(rev, &s, &c);
-    const TP A = wf_amplitude<TP>(w, k, kc, a.cf.invT);
-    const TP cp = A * TP(0.5) * (TP(1) + TP(w.cosi) * TP(w.cosi));
-    const TP cx = A * TP(w.cosi);
-    // h+ = A cp e^{-i Psi};  hx = -i A cx e^{-i Psi}
-    hp = {float(cp * c), float(-cp * s)};
-    hc = {float(-cx * s), float(-cx * c)};
+  for (int k = threadIdx.x; k < F; k += 256) {
+    float2 hp = {0.f, 0.f}, hc = {0.f, 0.f};
+    if (k > 0 && k >= a.cf.kmin && k < w.kend) {
+      const double kc = a.kcbrt[k], lk = a.lnk3[k];
+      TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst);
+      rev = frac1(rev);
+      TP s, c;
+      sincos_rev(rev, &s, &c);
+      const TP A = wf_amplitude<TP>(w, k, kc, a.cf.invT);
+      const TP cp = A * TP(0.5) * (TP(1) + TP(w.cosi) * TP(w.cosi));
+      const TP cx = A * TP(w.cosi);
+      // h+ = A cp e^{-i Psi};  hx = -i A cx e^{-i Psi}
+      hp = {float(cp * c), float(-cp * s)};
+      hc = {float(-cx * s), float(-cx * c)};
+    }
+    reinterpret_cast<float2*>(a.hp)[b * F + k] = hp;
+    reinterpret_cast<float2*>(a.hc)[b * F + k] = hc;
   }
-  reinterpret_cast<float2*>(a.hp)[b * F + k] = hp;
-  reinterpret_cast<float2*>(a.hc)[b * F + k] = hc;
 }
 
 // ------------------------------------------------------------ projection
@@ -178,9 +178,17 @@ struct WinArgs {
   const double* lnk3;
   const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
   const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
-  const WfScalars* wf;    // [B] (SRC 1)
-  const DetScalars* dsc;  // [B][D] (SRC 1)
+  const WfScalars* wf;    // [B] (SRC 1, 3)
+  const DetScalars* dsc;  // [B][D] (SRC 1, 3)
+  const float* nodes;     // [B][2][1024] surrogate node values (SRC 3)
+  const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
+  float logmm_max;        // fallback threshold (SRC 3)
 };
+
+// Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
+constexpr int kSurrNodes = 1024;
+constexpr double kSurrLnMfLo = -6.2146080984221914;   // ln(2e-3)
+constexpr double kSurrDlog = 4.6051701859880914 / 1023.0;  // ln(0.2/2e-3)/(NN-1)
 
 // Whitening factor for window bin k in [0, N/2]; sets status bits.
 template <class T>
@@ -208,7 +216,35 @@ __device__ __forceinline__ cpx<T> signal_bin(const WinArgs& a, const WfScalars& 
   return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
 }
 
+// Projected signal at window bin k from surrogate node values: binary64
+// Newtonian phase + interpolated phase residual (revolutions), amplitude
+// A_N(f_k) times the interpolated ratio.
+template <class T>
+__device__ __forceinline__ cpx<T> signal_bin_surr(const WinArgs& a, const WfScalars& w, const float* nd, T cpl, T cxx,
+                                                  double tauT, int k) {
+  if (k <= 0 || k < a.cf.kmin || k >= w.kend) return {T(0), T(0)};
+  const double kc = a.kcbrt[k], lk3 = a.lnk3[k];
+  // u = (ln(Ms k / T) - ln Mf_lo) / dlog, ln(Ms/T) = 3 ln v1 - ln pi
+  const float u = float((3.0 * w.lnv1 - 1.1447298858494002 + 3.0 * lk3 - kSurrLnMfLo) * (1.0 / kSurrDlog));
+  const float uc = fminf(fmaxf(u, 0.f), float(kSurrNodes - 1));
+  const int i = min(int(uc), kSurrNodes - 2);
+  const float tt = uc - float(i);
+  const float ratio = (1.f - tt) * nd[i] + tt * nd[i + 1];
+  const float dpsi = (1.f - tt) * nd[kSurrNodes + i] + tt * nd[kSurrNodes + i + 1];
+  const double v = w.v1 * kc;
+  const double iv = rcp_t(v);
+  const double iv2 = iv * iv;
+  double rev = w.a[0] * iv2 * iv2 * iv + double(dpsi) * (1.0 / (2.0 * kPi)) + w.pconst + double(k) * tauT;
+  rev = frac1(rev);
+  T sn, cs;
+  sincos_rev(T(rev), &sn, &cs);
+  const T A = T(a.cf.fs) * T(w.A0T) * rsqrt_t(T(kc)) * rcp_t(T(k)) * T(ratio);
+  return {A * (cpl * cs - cxx * sn), -A * (cpl * sn + cxx * cs)};
+}
+
 // SRC 0: whiten strain.  SRC 1: fused background + signal + whiten.
+// SRC 3: as SRC 1 with the signal from surrogate node values (plain model
+// where the predicted mismatch exceeds the threshold).
 // SRC 2: inject (out = bg window + irfft(hdet)); src is hdet [B][D][N/2+1].
 // Occupancy target: two workgroups per CU (VGPR budget 128 for 512 threads).
 template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
@@ -235,6 +271,7 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
 
   if constexpr (SRC != 2) {
     const float* x = (SRC == 0) ? a.src + bd * N : a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
+    static_assert(SRC >= 0 && SRC <= 3, "source");
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       float2 q;
@@ -255,8 +292,15 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
   const float* psd = a.psd + bd * a.cf.Fw;
   T cpl = T(0), cxx = T(0);
   double tauT = 0.0;
-  const WfScalars& wsh = a.wf[SRC == 1 ? b : 0];
-  if constexpr (SRC == 1) {
+  const WfScalars& wsh = a.wf[(SRC == 1 || SRC == 3) ? b : 0];
+  bool use_surr = false;
+  const float* nd = nullptr;
+  if constexpr (SRC == 3) {
+    use_surr = !(a.logmm[b] > a.logmm_max);
+    nd = a.nodes + b * 2 * kSurrNodes;
+    if (!use_surr && t == 0 && d == 0 && a.status) atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
+  }
+  if constexpr (SRC == 1 || SRC == 3) {
     const DetScalars dsh = a.dsc[bd];
     cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
     cxx = T(dsh.fx * wsh.cosi);
@@ -288,6 +332,14 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
       if constexpr (SRC == 1) {
         Xk = cadd(Xk, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, k));
         if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, km));
+      } else if constexpr (SRC == 3) {
+        if (use_surr) {
+          Xk = cadd(Xk, signal_bin_surr<T>(a, wsh, nd, cpl, cxx, tauT, k));
+          if (km != k) Xm = cadd(Xm, signal_bin_surr<T>(a, wsh, nd, cpl, cxx, tauT, km));
+        } else {
+          Xk = cadd(Xk, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, k));
+          if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, km));
+        }
       }
       Yk = cscale(Xk, whiten_gain<T>(a, psd, k, NC, flag));
       Ym = cscale(Xm, whiten_gain<T>(a, psd, km, NC, flag));
@@ -607,7 +659,7 @@ static void launch_window(const DevCfg& d, int64_t blocks, const WinArgs& a, hip
 }
 
 template <int SRC>
-static void launch_window_prec(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
+void launch_window_prec(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
   if (d.precision == 0) launch_window<float, float, false, SRC>(d, blocks, a, stream);
   else if (d.precision == 1) launch_window<float, double, false, SRC>(d, blocks, a, stream);
   else launch_window<double, double, true, SRC>(d, blocks, a, stream);
@@ -754,12 +806,12 @@ gw_status sample_params(gw_ctx* c, uint64_t seed, uint64_t first_index, int64_t 
 
 gw_status gen_fd_waveform(gw_ctx* c, const double* params, int64_t B, float* hp, float* hc, hipStream_t stream) {
   GW_CHECK_CTX(c);
-  if (B < 0 || B > 65535) return fail(c, GW_EINVAL, "B must be in [0, 65535]");
+  if (B < 0 || B > 0x7fffffff) return fail(c, GW_EINVAL, "bad B");
   if (B == 0) return GW_OK;
   if (!params || !hp || !hc) return fail(c, GW_EINVAL, "NULL pointer");
   if (!aligned16(params) || !aligned16(hp) || !aligned16(hc)) return fail(c, GW_EINVAL, "pointer not 16-byte aligned");
   WaveArgs a{c->dc, params, B, c->kcbrt, c->lnk3, hp, hc};
-  dim3 grid(unsigned((c->dc.F + 255) / 256), unsigned(B));
+  const dim3 grid = dim3(unsigned(B));
   if (c->dc.precision == 0) hipLaunchKernelGGL((k_gen_fd_waveform<float, false>), grid, dim3(256), 0, stream, a);
   else if (c->dc.precision == 1) hipLaunchKernelGGL((k_gen_fd_waveform<double, false>), grid, dim3(256), 0, stream, a);
   else hipLaunchKernelGGL((k_gen_fd_waveform<double, true>), grid, dim3(256), 0, stream, a);
@@ -833,6 +885,68 @@ gw_status whiten(gw_ctx* c, const float* strain, const float* psd, int64_t B, fl
   a.status = status;
   launch_window_prec<0>(c->dc, B * c->dc.n_det, a, stream);
   return check_launch(c, "k_window<whiten>");
+}
+
+static int64_t ws_nodes_bytes(int64_t B) { return ((B * 2 * 1024 * 4 + 255) / 256) * 256; }
+static int64_t ws_logmm_bytes(int64_t B) { return ((B * 4 + 255) / 256) * 256; }
+
+gw_status gw_workspace_size_surrogate(const gw_ctx* c, int64_t B, int64_t* bytes) {
+  gw_status s = gw_workspace_size(c, B, bytes);
+  if (s != GW_OK) return s;
+  *bytes += ws_nodes_bytes(B) + ws_logmm_bytes(B);
+  return GW_OK;
+}
+
+gw_status gw_generate_batch_surrogate(gw_ctx* c, gw_surrogate* sg, uint64_t seed, uint64_t batch_index, int64_t B,
+                                      const float* bg, int64_t L_bg, float* out, float* params_f32, uint32_t* status,
+                                      float log10_mm_max, void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (!sg) return fail(c, GW_EINVAL, "surrogate is NULL");
+  if (c->dc.approximant != 1) return fail(c, GW_EUNSUPPORTED, "the surrogate models approximant 1");
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!bg || !out || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(out) || !aligned16(workspace) || (params_f32 && !aligned16(params_f32)) ||
+      (status && !aligned4(status)))
+    return fail(c, GW_EINVAL, "misaligned pointer");
+  int64_t need = 0;
+  gw_workspace_size_surrogate(c, B, &need);
+  if (workspace_bytes < need) return fail(c, GW_EINVAL, "workspace too small");
+  const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
+  if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
+  if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
+  char* ws = static_cast<char*>(workspace);
+  double* params = reinterpret_cast<double*>(ws);
+  int64_t* offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
+  float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
+  WfScalars* wf = reinterpret_cast<WfScalars*>(ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B));
+  DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
+  float* nodes = reinterpret_cast<float*>(reinterpret_cast<char*>(dsc) + ws_det_bytes(c->dc, B));
+  float* logmm = reinterpret_cast<float*>(reinterpret_cast<char*>(nodes) + ws_nodes_bytes(B));
+  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status, wf, dsc};
+  hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
+  gw_status s = check_launch(c, "k_sample_params");
+  if (s != GW_OK) return s;
+  s = gw_surrogate_nodes(sg, params, B, nodes, logmm, stream);
+  if (s != GW_OK) return fail(c, s, std::string("surrogate: ") + gw_surrogate_last_error(sg));
+  s = welch_launch(c, bg, L_bg, offset, B, psd, stream);
+  if (s != GW_OK) return s;
+  WinArgs a = win_args(c);
+  a.src = bg;
+  a.L_bg = L_bg;
+  a.offset = offset;
+  a.params = params;
+  a.B = B;
+  a.psd = psd;
+  a.out = out;
+  a.status = status;
+  a.wf = wf;
+  a.dsc = dsc;
+  a.nodes = nodes;
+  a.logmm = logmm;
+  a.logmm_max = log10_mm_max;
+  launch_window_prec<3>(c->dc, B * c->dc.n_det, a, stream);
+  return check_launch(c, "k_window<surrogate>");
 }
 
 gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, const float* bg,

@@ -17,6 +17,7 @@ STATUS_NONFINITE_PSD = 1
 STATUS_NONPOSITIVE_PSD = 2
 STATUS_NONFINITE_DATA = 4
 STATUS_CUT_AT_NYQUIST = 8
+STATUS_SURROGATE_FALLBACK = 16
 N_PARAMS = 12
 (Q_N, Q_F, Q_P, Q_L, Q_K, Q_FW, Q_NDET, Q_NPARAMS) = range(8)
 
@@ -30,7 +31,8 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_surrogate_fit_skip", "gw_surrogate_standardise", "gw_surrogate_forward",
            "gw_surrogate_gradients", "gw_surrogate_train_step", "gw_surrogate_hidden",
            "gw_surrogate_set_head", "gw_surrogate_fit_head", "gw_surrogate_nodes",
-           "gw_surrogate_waveform", "gw_mismatch", "gw_surrogate_save", "gw_surrogate_load")
+           "gw_surrogate_waveform", "gw_mismatch", "gw_surrogate_save", "gw_surrogate_load",
+           "gw_surrogate_set_state", "gw_workspace_size_surrogate", "gw_generate_batch_surrogate")
 
 
 class GWConfig(ctypes.Structure):
@@ -91,6 +93,10 @@ def lib():
             "gw_mismatch": ([vp, vp, vp, vp, vp, i64, vp, vp], i32),
             "gw_surrogate_save": ([vp, ctypes.c_char_p], i32),
             "gw_surrogate_load": ([vp, ctypes.c_char_p], i32),
+            "gw_surrogate_set_state": ([vp, vp, vp, vp, vp, vp, vp], i32),
+            "gw_workspace_size_surrogate": ([vp, i64, ctypes.POINTER(i64)], i32),
+            "gw_generate_batch_surrogate": ([vp, vp, u64, u64, i64, vp, i64, vp, vp, vp, ctypes.c_float, vp,
+                                             i64, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -262,6 +268,29 @@ class Generator:
         _want(mm, torch.float64, (B,), "mm")
         self._check(lib().gw_mismatch(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
                                       _stream()), "gw_mismatch")
+
+    def alloc_workspace_surrogate(self, B, device="cuda"):
+        import torch
+        v = ctypes.c_int64()
+        self._check(lib().gw_workspace_size_surrogate(self._h, int(B), ctypes.byref(v)),
+                    "gw_workspace_size_surrogate")
+        return torch.empty((v.value + 7) // 8, dtype=torch.float64, device=device)
+
+    def generate_batch_surrogate(self, surrogate, seed, batch_index, B, bg, out, workspace, params_f32=None,
+                                 status=None, log10_mm_max=-3.0):
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_generate_batch_surrogate(self._h, surrogate._h, int(seed), int(batch_index), int(B),
+                                                      _ptr(bg), bg.shape[1], _ptr(out), _ptr(params_f32),
+                                                      _ptr(status), ctypes.c_float(log10_mm_max),
+                                                      _ptr(workspace), nbytes, _stream()),
+                    "gw_generate_batch_surrogate")
 
     def workspace_views(self, workspace, B):
         """(params float64 [12][B], offsets int64 [B]) inside a batch workspace."""

@@ -78,6 +78,17 @@ class Surrogate:
         head = np.ascontiguousarray(head, dtype=np.float32)
         self._check(lib().gw_surrogate_set_head(self._h, head.ctypes.data, head.size), "set_head")
 
+    def set_state(self, basis, mean, A, zmean, zstd, head):
+        """Non-network state from host arrays (see gw_surrogate_set_state)."""
+        arrs = [np.ascontiguousarray(basis, np.float32), np.ascontiguousarray(mean, np.float64),
+                np.ascontiguousarray(A, np.float32), np.ascontiguousarray(zmean, np.float32),
+                np.ascontiguousarray(zstd, np.float32), np.ascontiguousarray(head, np.float32)]
+        shapes = [(2, 64, NODES), (2, NODES), (N_FEAT, N_OUT), (N_OUT,), (N_OUT,), (HIDDEN + 1,)]
+        for a, sh in zip(arrs, shapes):
+            if a.shape != sh:
+                raise ValueError("state array shape %s, expected %s" % (a.shape, sh))
+        self._check(lib().gw_surrogate_set_state(self._h, *[a.ctypes.data for a in arrs]), "set_state")
+
     def save(self, path):
         self._check(lib().gw_surrogate_save(self._h, path.encode()), "save")
 

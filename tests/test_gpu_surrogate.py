@@ -30,6 +30,14 @@ def gen():
 
 
 def _params(gen, seed, n):
+    """Parameters drawn by the oracle (same Philox stream as the GPU), uploaded:
+    used wherever a result is compared with the oracle."""
+    p, _ = oracle.sample_params(inputs.config("surrogate"), seed, 0, n, gen.sizes["P"] + gen.sizes["N"])
+    return torch.from_numpy(p).to(DEV)
+
+
+def _params_gpu(gen, seed, n):
+    """Parameters drawn on the GPU, for measurements that need no oracle."""
     p = torch.empty((12, n), dtype=torch.float64, device=DEV)
     o = torch.empty(n, dtype=torch.int64, device=DEV)
     gen.sample_params(seed, 0, n, gen.sizes["P"] + gen.sizes["N"], p, o)
@@ -188,7 +196,7 @@ def trained(gen):
 def test_trained_surrogate_mismatch_and_gain(gen, trained):
     s, psd, stats = trained
     B = 8192
-    p = _params(gen, 4, B)  # held-out draws (different seed)
+    p = _params_gpu(gen, 4, B)  # held-out draws (different seed)
     mm, logmm = s.mismatch_vs_plain(p, psd)
     torch.cuda.synchronize()
     mm = mm.cpu().numpy()
@@ -231,10 +239,108 @@ def test_save_and_load_roundtrip(gen, trained, tmp_path):
     s.save(path)
     s2 = GS.Surrogate(gen, max_batch=256)
     s2.load(path)
-    p = _params(gen, 8, 64)
+    p = _params_gpu(gen, 8, 64)
     a = torch.empty((64, 2, 1024), dtype=torch.float32, device=DEV)
     b = torch.empty_like(a)
     s.nodes(p, a)
     s2.nodes(p, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def _state_from_oracle(seed=31, n_fit=1200):
+    """Surrogate state built on the CPU from oracle targets (numpy SVD and
+    least squares) plus seeded small MLP weights: an input both sides share."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cfg = inputs.config("surrogate")
+    th = np.stack([rng.uniform(*cfg["mc"], n_fit), rng.uniform(*cfg["q"], n_fit),
+                   rng.uniform(*cfg["chi"], n_fit), rng.uniform(*cfg["chi"], n_fit)], 1)
+    R = np.zeros((n_fit, 1024))
+    D = np.zeros((n_fit, 1024))
+    Fe = np.zeros((n_fit, 9))
+    for i in range(n_fit):
+        R[i], D[i] = OS.targets(*th[i])
+        Fe[i] = OS.features(*th[i, 1:])
+    basis = np.zeros((2, 64, 1024), np.float32)
+    mean = np.zeros((2, 1024))
+    C = []
+    for j, X in enumerate((R, D)):
+        mean[j] = X.mean(0)
+        _, _, Vt = np.linalg.svd(X - mean[j], full_matrices=False)
+        V = Vt[:64]
+        V = V * np.sign(V[np.arange(64), np.argmax(np.abs(V), axis=1)])[:, None]
+        basis[j] = V.astype(np.float32)
+        C.append((X - mean[j]) @ basis[j].astype(np.float64).T)
+    C = np.concatenate(C, axis=1)
+    A = np.linalg.lstsq(Fe, C, rcond=None)[0].astype(np.float32)
+    resid = C - Fe @ A.astype(np.float64)
+    zmean = resid.mean(0).astype(np.float32)
+    zstd = np.maximum(resid.std(0), 1e-6).astype(np.float32)
+    flat = (GS.init_weights(seed + 1) * 0.3).astype(np.float32)
+    return dict(basis=basis, mean=mean, A=A, zmean=zmean, zstd=zstd, flat=flat)
+
+
+def test_fused_surrogate_batch_matches_oracle(gen):
+    name = "surrogate"
+    cfg = inputs.config(name)
+    st = _state_from_oracle()
+    s = GS.Surrogate(gen, max_batch=64)
+    s.set_weights(st["flat"])
+    head = np.zeros(257, np.float32)
+    head[256] = -5.0          # predicted log10 mm = -5: no fallback
+    s.set_state(st["basis"], st["mean"], st["A"], st["zmean"], st["zstd"], head)
+    B = 6
+    bg = inputs.background(3, 1 << 22, cfg["fs"], seed=1)
+    bg_t = torch.from_numpy(bg).to(DEV)
+    z = gen.sizes
+    out = torch.empty((B, 3, z["N"]), dtype=torch.float32, device=DEV)
+    status = torch.empty(B, dtype=torch.int32, device=DEV)
+    ws = gen.alloc_workspace_surrogate(B)
+    gen.generate_batch_surrogate(s, 2, 7, B, bg_t, out, ws, status=status, log10_mm_max=-3.0)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.all(status.cpu().numpy() & gwgen.STATUS_SURROGATE_FALLBACK == 0)
+    p_o, o_o = oracle.sample_params(cfg, 2, 7 * B, B, bg.shape[1])
+    lo = np.array([cfg["mc"][0], cfg["q"][0], cfg["chi"][0], cfg["chi"][0]])
+    hi = np.array([cfg["mc"][1], cfg["q"][1], cfg["chi"][1], cfg["chi"][1]])
+    W = _oracle_weights(st["flat"])
+    zo = oracle.derived_sizes(cfg)
+    errs = []
+    for i in range(B):
+        p = p_o[:, i]
+        theta = p[:4].astype(np.float32).astype(np.float64)[None, :]
+        feat = OS.features(p[1], p[2], p[3])[None, :]
+        nodes = OS.nodes_from_state(theta, feat, W, st["A"].astype(np.float64), st["zmean"].astype(np.float64),
+                                    st["zstd"].astype(np.float64), st["basis"].astype(np.float64), st["mean"],
+                                    lo, hi)[0]
+        hp, hc = OS.reconstruct(cfg, p, nodes[0], nodes[1])
+        H = oracle.project_detectors(cfg, p, hp, hc)
+        y = oracle.inject(cfg, bg, int(o_o[i]), H)
+        psd = oracle.pipeline.sample_psd(cfg, bg, int(o_o[i]))
+        for d in range(3):
+            ref = oracle.whiten(y[d], oracle.interp_psd(psd[d], zo["r"]), cfg["fs"], cfg["f_min"])
+            errs.append(np.linalg.norm(o[i, d] - ref) / np.linalg.norm(ref))
+    _say("fused surrogate batch vs oracle: max rel L2 %.2e" % max(errs))
+    assert max(errs) < 1e-5
+
+
+def test_fused_surrogate_fallback_equals_plain(gen):
+    cfg = inputs.config("surrogate")
+    st = _state_from_oracle(n_fit=200)
+    s = GS.Surrogate(gen, max_batch=64)
+    s.set_weights(st["flat"])
+    head = np.zeros(257, np.float32)
+    head[256] = 5.0           # predicted log10 mm = +5: every sample falls back
+    s.set_state(st["basis"], st["mean"], st["A"], st["zmean"], st["zstd"], head)
+    B = 5
+    bg = inputs.background(3, 1 << 22, cfg["fs"], seed=1)
+    bg_t = torch.from_numpy(bg).to(DEV)
+    z = gen.sizes
+    a = torch.empty((B, 3, z["N"]), dtype=torch.float32, device=DEV)
+    b = torch.empty_like(a)
+    status = torch.empty(B, dtype=torch.int32, device=DEV)
+    gen.generate_batch_surrogate(s, 4, 1, B, bg_t, a, gen.alloc_workspace_surrogate(B), status=status)
+    gen.generate_batch(4, 1, B, bg_t, b, gen.alloc_workspace(B))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert np.all(status.cpu().numpy() & gwgen.STATUS_SURROGATE_FALLBACK)
