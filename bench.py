@@ -4,7 +4,11 @@ A step is one whole batch of the paper-scale workload: 2048 samples, three
 detectors (H1, L1, V1), 8 s windows at 2048 Hz, IMR-form waveforms, a Welch
 PSD per (sample, detector) from the 64 s of background preceding its window.
 Steps run back to back on the resident background (2^27 samples per detector)
-with every input already in HBM.  Prints one JSON line.
+with every input already in HBM; the timed steps are replays of the captured
+batch graph after the radix-order autotuner has run.  Also reported: the same
+steps issued eagerly, the surrogate path, and the uneven workload (16384
+signals over six (rate, duration) classes, one persistent launch per stage).
+Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -183,6 +187,71 @@ def surrogate_leg(gen, bg, args, K, W, dev):
 
 # ------------------------------------------------------------------- main
 
+def ragged_leg(bg2048, args, K, W, dev):
+    """Uneven workload: 16384 signals, (fs, T) in {1024, 2048} Hz x {4, 8, 16} s,
+    classes drawn uniformly; the 2048 Hz classes share the main background,
+    the 1024 Hz classes use one of 2^26 samples per detector."""
+    import numpy as np
+    import torch
+    from paper_2407_19048_amd import gwgen, inputs
+    classes = inputs.ragged_classes(precision=args.precision)
+    t0 = time.perf_counter()
+    bg1024 = torch.from_numpy(inputs.background(3, 1 << (args.log2_bg - 1), 1024.0, seed=3)).to(dev)
+    log("ragged: 1024 Hz background in %.1f s" % (time.perf_counter() - t0))
+    bgs = [bg1024 if c["fs"] == 1024.0 else bg2048 for c in classes]
+    Br = args.ragged_batch
+    cls = inputs.ragged_assignment(Br)
+    rg = gwgen.Ragged(classes, cls)
+    out = rg.alloc_out(device=dev)
+    ws = rg.alloc_workspace(device=dev)
+    pf = torch.empty((12, Br), dtype=torch.float32, device=dev)
+    st = torch.empty(Br, dtype=torch.int32, device=dev)
+    table = rg.autotune(bgs, out, ws, reps=3)
+    tuned = {"ord_window": rg.get_tuning(gwgen.RTUNE_ORD_WINDOW), "ord_welch": rg.get_tuning(gwgen.RTUNE_ORD_WELCH),
+             "grid_window": rg.get_tuning(gwgen.RTUNE_GRID_WINDOW),
+             "grid_welch": rg.get_tuning(gwgen.RTUNE_GRID_WELCH)}
+    log("ragged autotune %s -> %s" % (table, tuned))
+    graph = rg.graph(2, 0, bgs, out, ws, params_f32=pf, status=st)
+    for _ in range(W):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        graph.launch()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("non-finite ragged output")
+    Ke = min(K, 10)
+    t0 = time.perf_counter()
+    for i in range(Ke):
+        rg.generate(2, W + i, bgs, out, ws, pf, st)
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / Ke
+    graph.close()
+    # algorithmic bytes: D (P + N) read and D N written per signal
+    nbytes = 0
+    for c, n in zip(classes, np.bincount(cls, minlength=len(classes))):
+        P, N = int(c["psd_length"] * c["fs"]), int(c["t_window"] * c["fs"])
+        nbytes += int(n) * 3 * (P + 2 * N) * 4
+    ms = 1e3 * el / K
+    gbs = nbytes / (el / K) / 1e9
+    welch_best = min(table["welch"].values())
+    win_best = min(table["window"].values())
+    log("ragged: %.3f ms/batch, %.0f samples/s, %.0f GB/s algorithmic" % (ms, Br / (el / K), gbs))
+    return {
+        "workload": "uneven: %d signals, H1+L1+V1, (fs, T) uniform over {1024, 2048} Hz x {4, 8, 16} s, "
+                    "Welch over the 64 s before each window" % Br,
+        "value": round(Br * K / el, 1), "unit": "samples/s", "ms_per_step": round(ms, 4),
+        "eager_ms_per_step": round(eager_ms, 4), "hbm_frac_algorithmic": round(gbs / HBM_PEAK_GBS, 4),
+        "bytes_per_step": nbytes, "class_counts": np.bincount(cls, minlength=len(classes)).tolist(),
+        "stage_ms": {"welch": round(welch_best, 4), "window": round(win_best, 4)},
+        "autotune_ms": {"welch_ord%d_grid%d" % k: round(v, 4) for k, v in table["welch"].items()}
+        | {"window_ord%d" % k: round(v, 4) for k, v in table["window"].items()},
+        "tuned": tuned,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-batch", type=int, default=8192)
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--ragged-batch", type=int, default=16384)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy a buffer of this size three times "
                          "(calibrates HBM byte counters against a known transfer)")
@@ -235,20 +306,33 @@ def main():
     ws = gen.alloc_workspace(B, device=dev)
     seed = 2
 
+    tune = gen.autotune(B, bg, out, ws, reps=3)
+    tuned = {"ord_window": gen.get_tuning(gwgen.TUNE_ORD_WINDOW), "ord_welch": gen.get_tuning(gwgen.TUNE_ORD_WELCH)}
+    log("autotune %s -> %s" % (tune, tuned))
+    graph = gen.graph(seed, 0, B, bg, out, ws, params_f32=pf, status=status)
     for i in range(W):
-        gen.generate_batch(seed, i, B, bg, out, ws, pf, status)
+        graph.launch()
     torch.cuda.synchronize()
     log("warmup done")
     t0 = time.perf_counter()
     for i in range(K):
-        gen.generate_batch(seed, W + i, B, bg, out, ws, pf, status)
+        graph.launch()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    log("timed %d steps in %.3f s" % (K, elapsed))
+    log("timed %d graph steps in %.3f s" % (K, elapsed))
     value = B * K / elapsed
     ms_step = 1e3 * elapsed / K
     if not bool(torch.isfinite(out).all()):
         raise RuntimeError("non-finite output")
+    # the same batches issued eagerly (three launches per step), for comparison
+    Ke = min(K, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(Ke):
+        gen.generate_batch(seed, W + i, B, bg, out, ws, pf, status)
+    torch.cuda.synchronize()
+    eager_ms = 1e3 * (time.perf_counter() - t0) / Ke
+    graph.close()
 
     # dominant kernel: segmented Welch, timed on its own with HIP events on the
     # stream the library launches on (torch's current stream)
@@ -289,6 +373,10 @@ def main():
     if not args.no_surrogate:
         surrogate = surrogate_leg(gen, bg, args, K, W, dev)
 
+    ragged = None
+    if not args.no_ragged:
+        ragged = ragged_leg(bg, args, K, W, dev)
+
     rec = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -309,6 +397,10 @@ def main():
             "global_batch": B, "window_samples": z["N"], "psd_stretch_samples": z["P"],
             "background_samples_per_det": int(bg.shape[1]), "precision_mode": args.precision,
             "path": "plain",
+            "issue": "hip graph replay",
+            "eager_ms_per_step": round(eager_ms, 4),
+            "autotune_ms": {k: round(v, 4) for k, v in tune.items()},
+            "tuned": tuned,
             "step_hbm_frac_algorithmic": round(step_gbs / HBM_PEAK_GBS, 4),
         },
         "roofline": {
@@ -322,6 +414,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "surrogate": surrogate,
+        "ragged": ragged,
     }
     print(json.dumps(rec), flush=True)
 

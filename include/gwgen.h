@@ -200,6 +200,117 @@ gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
                             void* workspace, int64_t workspace_bytes,
                             hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Captured batch pipelines (HIP graphs).  A gw_graph replays the kernels of
+ * one batch with the pointers given at creation; every launch then advances
+ * a batch counter kept in the workspace, so replay r (counting from 0 after
+ * creation or gw_graph_set_batch(b0)) produces exactly what the eager call
+ * with batch_index = b0 + r produces.  The caller keeps bg, out, params_f32,
+ * status and workspace alive and unmoved while the graph exists.  Creation
+ * captures on a private stream and synchronises; tune (gw_set_tuning /
+ * gw_autotune) before creating a graph, since the graph keeps the kernel
+ * variants chosen at capture.
+ * ------------------------------------------------------------------------ */
+typedef struct gw_graph gw_graph;
+/* Graph of gw_generate_batch(seed, first_batch + r, B, ...). */
+gw_status gw_graph_create(gw_ctx* ctx, uint64_t seed, uint64_t first_batch,
+                          int64_t B, const float* bg, int64_t L_bg,
+                          float* out, float* params_f32, uint32_t* status,
+                          void* workspace, int64_t workspace_bytes,
+                          gw_graph** graph);
+/* Replay one batch on `stream` (asynchronous). */
+gw_status gw_graph_launch(gw_graph* graph, hipStream_t stream);
+/* Queue a reset of the batch counter to batch_index on `stream`. */
+gw_status gw_graph_set_batch(gw_graph* graph, uint64_t batch_index, hipStream_t stream);
+const char* gw_graph_last_error(const gw_graph* graph);
+gw_status gw_graph_destroy(gw_graph* graph);
+
+/* Kernel variants.  GW_TUNE_ORD_*: 0 puts the FFT's small radix pass last,
+ * 1 puts it first (same result up to rounding; which is faster depends on
+ * the size).  Binary64 kernels (precision 2) have order 0 only. */
+#define GW_TUNE_ORD_WINDOW 1
+#define GW_TUNE_ORD_WELCH  2
+gw_status gw_set_tuning(gw_ctx* ctx, int32_t key, int64_t value);
+gw_status gw_get_tuning(const gw_ctx* ctx, int32_t key, int64_t* value);
+/* Autotuner: runs one batch of size B, then times the Welch and the fused
+ * window kernel under each radix order over `reps` launches on a private
+ * stream (synchronous) and keeps the faster of each.  report (host double
+ * [4], nullable) receives the mean ms of Welch order 0, Welch order 1,
+ * window order 0, window order 1.  Overwrites out and workspace. */
+gw_status gw_autotune(gw_ctx* ctx, int64_t B, const float* bg, int64_t L_bg,
+                      float* out, void* workspace, int64_t workspace_bytes,
+                      int32_t reps, double* report);
+
+/* ------------------------------------------------------------------------
+ * Uneven (ragged) batches: signals of several size classes in one batch.
+ * Each class is a full gw_config (its own fs, t_window, psd_length, fftlen,
+ * f_min); all classes share n_det, det_id, approximant, prior ranges and
+ * precision (0 or 1), and need N >= 2 L.  Up to GW_RAGGED_MAX_CLASSES
+ * classes.  The class of each of the B signal slots is fixed when the
+ * handle is created (host array cls[B]); parameters, offsets and noise are
+ * drawn per batch exactly as gw_generate_batch draws them for the class's
+ * configuration at global index batch_index*B + i, with parameter row 11
+ * set to the class index.  Each stage is ONE persistent launch over all
+ * classes: a Welch kernel and a fused window kernel pull groups of
+ * (signal, detector) items of one class from an atomic queue, largest
+ * transforms first; small transforms share a workgroup as sub-blocks.
+ * Output: one flat float buffer; signal i occupies [n_det][N_i] floats from
+ * out_offset[i] (gw_ragged_offsets).
+ * ------------------------------------------------------------------------ */
+#define GW_RAGGED_MAX_CLASSES 8
+typedef struct gw_ragged gw_ragged;
+/* Validate the classes, build the work plan (descriptors, queues, tables)
+ * on the current device.  Allocates device memory; not for the hot path. */
+gw_status gw_ragged_create(const gw_config* classes, int32_t n_classes,
+                           const int32_t* cls, int64_t B, gw_ragged** out);
+gw_status gw_ragged_destroy(gw_ragged* r);
+const char* gw_ragged_last_error(const gw_ragged* r);
+#define GW_RQ_B          0  /* signal slots                                  */
+#define GW_RQ_OUT_FLOATS 1  /* floats of the flat output                     */
+#define GW_RQ_PSD_FLOATS 2  /* floats of the flat PSD region                 */
+#define GW_RQ_WORKSPACE  3  /* workspace bytes                               */
+#define GW_RQ_PSD_OFFSET 4  /* byte offset of the PSD region in the workspace */
+#define GW_RQ_NCLASSES   5
+gw_status gw_ragged_query(const gw_ragged* r, int32_t key, int64_t* value);
+/* Host arrays [B+1]: float offsets of each signal's output block and of its
+ * [n_det][L/2+1] PSD block (the last entry is the total). */
+gw_status gw_ragged_offsets(const gw_ragged* r, int64_t* out_offset, int64_t* psd_offset);
+/* One ragged batch.  bg, L_bg: host arrays [n_classes] of device
+ * background pointers (float [n_det][L_bg[c]], 4-byte aligned) and lengths;
+ * classes with equal fs normally share one background.  out: float
+ * [GW_RQ_OUT_FLOATS]; params_f32: float [12][B] or NULL; status: uint32
+ * [B] or NULL.  Workspace layout: params double [12][B], offsets int64 [B],
+ * then per-sample constants, the queue/batch counters, and the PSDs from
+ * byte GW_RQ_PSD_OFFSET. */
+gw_status gw_generate_ragged(gw_ragged* r, uint64_t seed, uint64_t batch_index,
+                             const float* const* bg, const int64_t* L_bg,
+                             float* out, float* params_f32, uint32_t* status,
+                             void* workspace, int64_t workspace_bytes,
+                             hipStream_t stream);
+/* Graph of gw_generate_ragged(seed, first_batch + r, ...); see gw_graph. */
+gw_status gw_ragged_graph_create(gw_ragged* r, uint64_t seed, uint64_t first_batch,
+                                 const float* const* bg, const int64_t* L_bg,
+                                 float* out, float* params_f32, uint32_t* status,
+                                 void* workspace, int64_t workspace_bytes,
+                                 gw_graph** graph);
+/* Ragged kernel variants: radix orders as for gw_set_tuning, and the
+ * persistent grid of each stage in workgroups per compute unit (1..8). */
+#define GW_RTUNE_ORD_WINDOW 1
+#define GW_RTUNE_ORD_WELCH  2
+#define GW_RTUNE_GRID_WINDOW 3
+#define GW_RTUNE_GRID_WELCH  4
+gw_status gw_ragged_set_tuning(gw_ragged* r, int32_t key, int64_t value);
+gw_status gw_ragged_get_tuning(const gw_ragged* r, int32_t key, int64_t* value);
+/* Autotuner of the ragged stages (synchronous, private stream): times the
+ * Welch stage over radix order x grid {1, 2, 4 per CU} and the window stage
+ * over radix order, `reps` launches each, and keeps the fastest.  report
+ * (host double [8], nullable): mean ms of Welch (order 0, grid 1, 2, 4),
+ * (order 1, grid 1, 2, 4), then window order 0 and 1.  Overwrites out and
+ * workspace. */
+gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t* L_bg,
+                             float* out, void* workspace, int64_t workspace_bytes,
+                             int32_t reps, double* report);
+
 
 /* ------------------------------------------------------------------------
  * Learned waveform surrogate (an addition of this library to the waveform

@@ -15,11 +15,16 @@ Readings where the paper is silent:
     DFT coefficients);
   * injection in the time domain, y_d = bg_d[o+P : o+P+N] + irfft_N(H_d);
   * whitened output: float64 [B][D][N].
+  * uneven batches (several window lengths and sample rates in one batch):
+    slot i of a batch of B slots is an ordinary sample of its own class's
+    configuration, drawn at global index batch_index * B + i with that
+    class's background; parameter row 11 holds the class index.
 """
 
 import numpy as np
 
 from .detectors import antenna_patterns, detector_geometry, time_delays
+from .priors import sample_params
 from .spectral import interp_psd, welch_psd, whiten
 from .waveform import fd_waveform
 
@@ -107,3 +112,31 @@ def generate_batch(cfg, bg, params, offsets):
     for i in range(B):
         out[i] = generate_sample(cfg, bg, params[:, i], int(offsets[i]))
     return out
+
+
+def ragged_draws(classes, cls, seed, batch_index, bg_lengths, slots=None):
+    """Parameters [12][B] and offsets [B] of an uneven batch (columns of
+    slots outside `slots` are left zero when `slots` is given)."""
+    B = len(cls)
+    params = np.zeros((12, B), dtype=np.float64)
+    offsets = np.zeros(B, dtype=np.int64)
+    for i in (range(B) if slots is None else slots):
+        c = int(cls[i])
+        p, o = sample_params(classes[c], seed, batch_index * B + i, 1, bg_lengths[c])
+        params[:, i] = p[:, 0]
+        params[11, i] = float(c)
+        offsets[i] = o[0]
+    return params, offsets
+
+
+def generate_ragged(classes, cls, seed, batch_index, bgs, slots=None):
+    """Uneven batch.  classes: list of configurations; cls: class index per
+    slot [B]; bgs: background per class.  Returns (outputs, params [12][B],
+    offsets [B]) with outputs[i] float64 [D][N_i] for every slot, or for the
+    slots listed in `slots` (then only their parameter columns are filled)."""
+    params, offsets = ragged_draws(classes, cls, seed, batch_index, [b.shape[1] for b in bgs], slots)
+    outs = {}
+    for i in (range(len(cls)) if slots is None else slots):
+        c = int(cls[i])
+        outs[i] = generate_sample(classes[c], bgs[c], params[:, i], int(offsets[i]))
+    return outs, params, offsets

@@ -133,34 +133,49 @@ template <int R, int DIR, class T> __device__ __forceinline__ void dftR(cpx<T>* 
   else dft2<DIR>(a);
 }
 
-// Radix plan: NP16 radix-16 passes followed by one pass of radix RL (1: none).
+// Radix plan: NP16 radix-16 passes and, when NC is not a power of 16, one
+// pass of radix RL.  ORD 0 runs the small pass last, ORD 1 first (the two
+// orderings trade LDS access patterns; an autotuner picks one per size).
 template <int NC> struct FftPlan {
   static constexpr int NP16 = (NC >= 65536) ? 4 : (NC >= 4096) ? 3 : (NC >= 256) ? 2 : 1;
   static constexpr int RL = NC / (NP16 == 4 ? 65536 : NP16 == 3 ? 4096 : NP16 == 2 ? 256 : 16);
   static constexpr int NPASS = NP16 + (RL > 1 ? 1 : 0);
-  static constexpr int RLAST = RL > 1 ? RL : 16;
   static constexpr int NT = NC / 16;
   static_assert(NC == 2048 || NC == 4096 || NC == 8192 || NC == 16384, "unsupported FFT size");
 };
 
-template <int NC, int PASS> struct PassInfo {
+template <int NC, int PASS, int ORD = 0> struct PassInfo {
   using P = FftPlan<NC>;
-  static constexpr int R = (PASS < P::NP16) ? 16 : P::RL;
-  static constexpr int NS = (PASS == 0) ? 1 : (PASS == 1) ? 16 : (PASS == 2) ? 256 : 4096;
+  static constexpr bool SMALL_FIRST = (ORD == 1) && (P::RL > 1);
+  static constexpr int R = SMALL_FIRST ? (PASS == 0 ? P::RL : 16) : ((PASS < P::NP16) ? 16 : P::RL);
+  static constexpr int p16 = SMALL_FIRST ? (PASS == 0 ? 0 : PASS - 1) : PASS;
+  static constexpr int NS = SMALL_FIRST ? (PASS == 0 ? 1 : P::RL * (p16 == 0 ? 1 : p16 == 1 ? 16 : 256))
+                                        : ((PASS == 0) ? 1 : (PASS == 1) ? 16 : (PASS == 2) ? 256 : 4096);
 };
 
+template <int NC, int ORD> struct PlanEnds {
+  static constexpr int RFIRST = PassInfo<NC, 0, ORD>::R;
+  static constexpr int RLAST = PassInfo<NC, FftPlan<NC>::NPASS - 1, ORD>::R;
+};
+
+// Register slot of input x[t + NT*j] (j < 16) before the first pass.
+template <int NC, int ORD = 0> __host__ __device__ constexpr int fft_in_slot(int j) {
+  constexpr int R0 = PlanEnds<NC, ORD>::RFIRST, NB = 16 / R0;
+  return (j % NB) * R0 + j / NB;
+}
+
 // Output bin held in element e after the last pass.
-template <int NC> __device__ __forceinline__ int fft_out_index(int t, int e) {
-  constexpr int R = FftPlan<NC>::RLAST, NT = FftPlan<NC>::NT;
+template <int NC, int ORD = 0> __device__ __forceinline__ int fft_out_index(int t, int e) {
+  constexpr int R = PlanEnds<NC, ORD>::RLAST, NT = FftPlan<NC>::NT;
   return t + NT * (e / R) + (e % R) * (NC / R);
 }
 
 // Twiddle providers: return the forward twiddle exp(-2 pi i r k / (NS R)).
 // Table form: tw[n] = exp(-2 pi i n / NC).
-template <class T, int NC> struct TableTwiddle {
+template <class T, int NC, int ORD = 0> struct TableTwiddle {
   const cpx<T>* __restrict__ tw;
   template <int PASS> __device__ __forceinline__ cpx<T> get(int m, int r, int k) const {
-    constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS;
+    constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS;
     return tw[(r * k) * (NC / (NS * R))];
   }
 };
@@ -169,10 +184,10 @@ template <class T, int NC> struct TableTwiddle {
 // the table and the other powers are products of at most three of them
 // (rounding error a few ulp).  Used where twiddle loads would otherwise
 // dominate the load count and register pressure.
-template <class T, int NC> struct PowTwiddle {
+template <class T, int NC, int ORD = 0> struct PowTwiddle {
   const cpx<T>* __restrict__ tw;
   template <int PASS, int R> __device__ __forceinline__ void all(int k, cpx<T>* w) const {
-    constexpr int NS = PassInfo<NC, PASS>::NS;
+    constexpr int NS = PassInfo<NC, PASS, ORD>::NS;
     constexpr int STEP = NC / (NS * R);
     const int i1 = k * STEP;
     w[1] = tw[i1];
@@ -200,16 +215,16 @@ template <class T, int NC> struct PowTwiddle {
 };
 
 template <class TW> struct TwiddleIsPow { static constexpr bool value = false; };
-template <class T, int NC> struct TwiddleIsPow<PowTwiddle<T, NC>> { static constexpr bool value = true; };
+template <class T, int NC, int ORD> struct TwiddleIsPow<PowTwiddle<T, NC, ORD>> { static constexpr bool value = true; };
 
 // One Stockham pass.  READ: take input from LDS (else registers already hold
 // it).  WRITE: scatter the output to LDS (else it stays in registers in the
 // final layout).  A barrier separates this pass's LDS reads from its writes;
 // the caller must ensure the LDS buffer is free before a pass that WRITEs
 // without READing.
-template <class T, int NC, int PASS, int DIR, bool READ, bool WRITE, class TW>
+template <class T, int NC, int PASS, int DIR, bool READ, bool WRITE, int ORD, class TW>
 __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
-  constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS;
+  constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS;
   constexpr int NT = NC / 16, NB = 16 / R, STRIDE = NC / R;
   if constexpr (READ) {
 #pragma unroll
@@ -258,20 +273,20 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
 }
 
 // Whole transform.  FIRST_FROM_LDS: the first pass reads its input from LDS
-// in natural order (else v holds it as v[r] = x[t + NT r]).  The result stays
-// in registers in the final layout (see fft_out_index).  Ends with LDS still
-// being read by other threads: barrier before reusing it.
-template <class T, int NC, int DIR, bool FIRST_FROM_LDS, class TW>
+// in natural order (else v holds it: x[t + NT j] in slot fft_in_slot(j)).
+// The result stays in registers in the final layout (see fft_out_index).
+// Ends with LDS still being read by other threads: barrier before reusing it.
+template <class T, int NC, int DIR, bool FIRST_FROM_LDS, int ORD = 0, class TW>
 __device__ __forceinline__ void block_fft(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
   using P = FftPlan<NC>;
-  fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true>(v, sre, sim, t, tw);
+  fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true, ORD>(v, sre, sim, t, tw);
   if constexpr (P::NPASS == 3) {
-    fft_pass<T, NC, 1, DIR, true, true>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 2, DIR, true, false>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 2, DIR, true, false, ORD>(v, sre, sim, t, tw);
   } else {
-    fft_pass<T, NC, 1, DIR, true, true>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 2, DIR, true, true>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 3, DIR, true, false>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 2, DIR, true, true, ORD>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 3, DIR, true, false, ORD>(v, sre, sim, t, tw);
   }
 }
 

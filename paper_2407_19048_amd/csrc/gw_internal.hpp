@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 
 #include "gw_physics.hpp"
@@ -18,7 +19,19 @@ struct gw_ctx {
   std::string err;
 };
 
+// A captured batch pipeline; each launch advances the device batch counter.
+struct gw_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t* batch = nullptr;  // device batch index inside the caller's workspace
+  std::string err;
+};
+
 namespace gw {
 gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg);
 gw_status ctx_check_launch(gw_ctx* c, const char* what);
+// Host validation of a configuration into device constants (nothing launched).
+gw_status validate_config(const gw_config* g, DevCfg* dc, std::string* why);
+gw_status capture_graph(const std::function<gw_status(hipStream_t)>& enqueue, uint64_t* batch, uint64_t first,
+                        gw_graph** out, std::string* why);
 }  // namespace gw

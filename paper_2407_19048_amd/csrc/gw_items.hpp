@@ -1,0 +1,375 @@
+// Per-item device code shared by the batch kernels and the persistent
+// ragged kernels: the window item (rfft -> signal -> whiten -> irfft) and the
+// Welch item, each run by the NC/16 threads of a (sub-)block on its own LDS
+// planes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gw_fft.hpp"
+#include "gw_physics.hpp"
+#include "../../include/gwgen.h"
+
+namespace gw {
+
+// ---------------------------------------- window kernels (FFT of length N)
+// Prior draws for global sample index g (the densities of Table 1 with the
+// ranges in c), the window's background offset in [0, span), status
+// initialisation, and the per-sample constants of the fused window kernel.
+// Row 11 of the parameters receives p11.
+__device__ __forceinline__ void draw_sample(const DevCfg& c, uint64_t seed, uint64_t g, int64_t i, int64_t B,
+                                            int64_t span, double p11, double* params, int64_t* offset,
+                                            float* params_f32, uint32_t* status, WfScalars* wf, DetScalars* dsc) {
+#pragma clang fp contract(off)
+  double u[11];
+#pragma unroll
+  for (int s = 0; s < 11; ++s) u[s] = philox_uniform(seed, g, uint32_t(s));
+  const double uo = philox_uniform(seed, g, 12u);
+  double p[12];
+  p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
+  p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
+  p[2] = c.chi[0] + u[2] * (c.chi[1] - c.chi[0]);
+  p[3] = c.chi[0] + u[3] * (c.chi[1] - c.chi[0]);
+  const double a3 = c.dl[0] * c.dl[0] * c.dl[0], b3 = c.dl[1] * c.dl[1] * c.dl[1];
+  p[4] = pow(a3 + u[4] * (b3 - a3), 1.0 / 3.0);
+  p[5] = acos(2.0 * u[5] - 1.0);
+  p[6] = 2.0 * kPi * u[6];
+  p[7] = asin(2.0 * u[7] - 1.0);
+  p[8] = kPi * u[8];
+  p[9] = 2.0 * kPi * u[9];
+  p[10] = c.T - 1.5 + u[10] * 1.0;
+  p[11] = p11;
+#pragma unroll
+  for (int r = 0; r < 12; ++r) params[r * B + i] = p[r];
+  offset[i] = int64_t(floor(uo * double(span)));
+  if (params_f32) {
+#pragma unroll
+    for (int r = 0; r < 12; ++r) params_f32[r * B + i] = float(p[r]);
+  }
+  if (status) {
+    const double eta = p[1] / ((1.0 + p[1]) * (1.0 + p[1]));
+    const double Ms = p[0] * pow(eta, -0.6) * kMsunSec;
+    const double f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
+    status[i] = f_cut > 0.5 * c.fs ? GW_STATUS_CUT_AT_NYQUIST : 0u;
+  }
+  if (wf) {
+    WfScalars w;
+    wf_setup(params, B, i, c, w);
+    wf[i] = w;
+    for (int d = 0; d < c.n_det; ++d) dsc[i * c.n_det + d] = det_response(c.det[d], w.ra, w.dec, w.psi, w.tc);
+  }
+}
+
+// Load through the constant address space: for memory that no thread writes
+// while the kernel runs.  A uniform address then becomes a scalar load even
+// after earlier stores in the same kernel.
+template <class T>
+__device__ __forceinline__ T load_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  typedef const __attribute__((address_space(4))) uint32_t* cword_ptr;
+  const cword_ptr q = (cword_ptr)(p);
+  T v;
+  uint32_t* o = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) o[i] = q[i];
+  return v;
+}
+
+struct WinArgs {
+  DevCfg cf;
+  const float* src;       // strain [B][D][N] (SRC 0, 2) or background (SRC 1)
+  int64_t L_bg;
+  const float* bg;        // background for inject (SRC 2)
+  const int64_t* offset;
+  const double* params;
+  int64_t B;
+  const float* psd;       // [B][D][Fw]
+  float* out;
+  uint32_t* status;
+  const double* kcbrt;
+  const double* lnk3;
+  const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
+  const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
+  const WfScalars* wf;    // [B] (SRC 1, 3)
+  const DetScalars* dsc;  // [B][D] (SRC 1, 3)
+  const float* nodes;     // [B][2][1024] surrogate node values (SRC 3)
+  const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
+  float logmm_max;        // fallback threshold (SRC 3)
+};
+
+// Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
+constexpr int kSurrNodes = 1024;
+constexpr double kSurrLnMfLo = -6.2146080984221914;   // ln(2e-3)
+constexpr double kSurrDlog = 4.6051701859880914 / 1023.0;  // ln(0.2/2e-3)/(NN-1)
+
+// Whitening factor for window bin k in [0, N/2]; sets status bits.
+template <class T>
+__device__ __forceinline__ T whiten_gain(const DevCfg& cf, const float* psd, int k, int NC, uint32_t& flag) {
+  if (k == 0 || k >= NC || k < cf.kmin) return T(0);
+  const int i = k >> cf.log2_ratio;
+  const T tt = T(k - (i << cf.log2_ratio)) * T(cf.inv_ratio);
+  const T S = (T(1) - tt) * T(psd[i]) + tt * T(psd[i + 1]);
+  if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
+  if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
+  return rsqrt_t(T(cf.fs) * S * T(0.5));
+}
+
+// Projected signal (DFT coefficients) at window bin k, generated in registers.
+template <class T, class TP, bool FULL>
+__device__ __forceinline__ cpx<T> signal_bin(const DevCfg& cf, const WinArgs& a, const WfScalars& w, T cpl, T cxx,
+                                             double tauT, int k) {
+  if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
+  const double kc = a.kcbrt[k], lk = a.lnk3[k];
+  TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
+  rev = frac1(rev);
+  T s, c;
+  sincos_rev(T(rev), &s, &c);
+  const T A = T(cf.fs) * wf_amplitude<T>(w, k, kc, cf.invT);
+  // fs A (cpl - i cxx)(c - i s)
+  return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
+}
+
+// Projected signal at window bin k from surrogate node values: binary64
+// Newtonian phase + interpolated phase residual (revolutions), amplitude
+// A_N(f_k) times the interpolated ratio.
+template <class T>
+__device__ __forceinline__ cpx<T> signal_bin_surr(const DevCfg& cf, const WinArgs& a, const WfScalars& w,
+                                                  const float* nd, T cpl, T cxx, double tauT, int k) {
+  if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
+  const double kc = a.kcbrt[k], lk3 = a.lnk3[k];
+  // u = (ln(Ms k / T) - ln Mf_lo) / dlog, ln(Ms/T) = 3 ln v1 - ln pi
+  const float u = float((3.0 * w.lnv1 - 1.1447298858494002 + 3.0 * lk3 - kSurrLnMfLo) * (1.0 / kSurrDlog));
+  const float uc = fminf(fmaxf(u, 0.f), float(kSurrNodes - 1));
+  const int i = min(int(uc), kSurrNodes - 2);
+  const float tt = uc - float(i);
+  const float ratio = (1.f - tt) * nd[i] + tt * nd[i + 1];
+  const float dpsi = (1.f - tt) * nd[kSurrNodes + i] + tt * nd[kSurrNodes + i + 1];
+  const double v = w.v1 * kc;
+  const double iv = rcp_t(v);
+  const double iv2 = iv * iv;
+  double rev = w.a[0] * iv2 * iv2 * iv + double(dpsi) * (1.0 / (2.0 * kPi)) + w.pconst + double(k) * tauT;
+  rev = frac1(rev);
+  T sn, cs;
+  sincos_rev(T(rev), &sn, &cs);
+  const T A = T(cf.fs) * T(w.A0T) * rsqrt_t(T(kc)) * rcp_t(T(k)) * T(ratio);
+  return {A * (cpl * cs - cxx * sn), -A * (cpl * sn + cxx * cs)};
+}
+
+// One window item (sample b, detector d) handled by the NC/16 threads t of a
+// (sub-)block, with its own LDS planes.
+// SRC 0: whiten strain (x = strain row).  SRC 1: background + in-register
+// signal + whiten (x = background at o + P).  SRC 3: as SRC 1 with the signal
+// from surrogate node values (plain model where the predicted mismatch
+// exceeds the threshold).  SRC 2: inject (hrow = hdet row, nz = noise window).
+// `active` false: compute on the given (valid) item but store nothing, so
+// that idle sub-blocks still meet every block barrier.
+template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
+__device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, int t, int64_t b, int d,
+                                            const float* x, const float* hrow, const float* nz, const float* psd,
+                                            float* o, const cpx<T>* twtab, const cpx<T>* twr, T* sre, T* sim,
+                                            bool active, uint32_t* sflag) {
+  constexpr int NT = NC / 16;
+  static_assert(SRC >= 0 && SRC <= 3, "source");
+  PowTwiddle<T, NC, ORD> tw{twtab};
+  cpx<T> v[16];
+  uint32_t flag = 0;
+  if constexpr (SRC != 2) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      float2 q;
+      __builtin_memcpy(&q, x + 2 * (t + NT * j), sizeof(q));
+      v[fft_in_slot<NC, ORD>(j)] = {T(q.x), T(q.y)};
+    }
+    block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = lpad(fft_out_index<NC, ORD>(t, e));
+      sre[i] = v[e].x;
+      sim[i] = v[e].y;
+    }
+    __syncthreads();
+  }
+
+  T cpl = T(0), cxx = T(0);
+  double tauT = 0.0;
+  WfScalars wsh;
+  if constexpr (SRC == 1 || SRC == 3) wsh = load_const(a.wf + b);
+  bool use_surr = false;
+  const float* nd = nullptr;
+  if constexpr (SRC == 3) {
+    use_surr = !(load_const(a.logmm + b) > a.logmm_max);
+    nd = a.nodes + b * 2 * kSurrNodes;
+    if (active && !use_surr && t == 0 && d == 0 && a.status)
+      atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
+  }
+  if constexpr (SRC == 1 || SRC == 3) {
+    const DetScalars dsh = load_const(a.dsc + (b * cf.n_det + d));
+    cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
+    cxx = T(dsh.fx * wsh.cosi);
+    tauT = dsh.tau * cf.invT;
+  }
+  const float2* hsrc = reinterpret_cast<const float2*>(hrow);
+
+  // pairs (k, NC - k) for k in [0, NC/2]
+#pragma unroll 1
+  for (int i = 0; i <= 8; ++i) {
+    const int k = t + NT * i;
+    if (k > NC / 2) break;
+    const int km = NC - k;
+    const cpx<T> W = twr[k];  // exp(-2 pi i k / N)
+    cpx<T> Yk, Ym;
+    if constexpr (SRC == 2) {
+      const float2 h0 = hsrc[k], h1 = hsrc[km];
+      Yk = {T(h0.x), T(h0.y)};
+      Ym = {T(h1.x), T(h1.y)};
+      if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
+    } else {
+      const int ia = lpad(k), ib = lpad(km & (NC - 1));
+      const cpx<T> A = {sre[ia], sim[ia]};
+      const cpx<T> Bm = {sre[ib], sim[ib]};
+      const cpx<T> s = cadd(A, cconj(Bm));
+      const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
+      cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
+      cpx<T> Xm = {T(0.5) * (s.x - u.y), T(0.5) * (-s.y - u.x)};
+      if constexpr (SRC == 1) {
+        Xk = cadd(Xk, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, k));
+        if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, km));
+      } else if constexpr (SRC == 3) {
+        if (use_surr) {
+          Xk = cadd(Xk, signal_bin_surr<T>(cf, a, wsh, nd, cpl, cxx, tauT, k));
+          if (km != k) Xm = cadd(Xm, signal_bin_surr<T>(cf, a, wsh, nd, cpl, cxx, tauT, km));
+        } else {
+          Xk = cadd(Xk, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, k));
+          if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, km));
+        }
+      }
+      Yk = cscale(Xk, whiten_gain<T>(cf, psd, k, NC, flag));
+      Ym = cscale(Xm, whiten_gain<T>(cf, psd, km, NC, flag));
+      if (km == k) Ym = Yk;
+    }
+    // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
+    const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
+    const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
+    const int ia = lpad(k);
+    sre[ia] = p.x - q.y;
+    sim[ia] = p.y + q.x;
+    if (k != 0 && km != k) {
+      const int ib = lpad(km);
+      sre[ib] = p.x + q.y;
+      sim[ib] = -p.y + q.x;
+    }
+  }
+  __syncthreads();
+  block_fft<T, NC, +1, true, ORD>(v, sre, sim, t, tw);
+  const T sc = T(1) / T(NC);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int n = fft_out_index<NC, ORD>(t, e);
+      float2 y = {float(v[e].x * sc), float(v[e].y * sc)};
+      if constexpr (SRC == 2) {
+        y.x += nz[2 * n];
+        y.y += nz[2 * n + 1];
+      }
+      reinterpret_cast<float2*>(o)[n] = y;
+    }
+    if (flag) atomicOr(sflag, flag);
+  }
+}
+
+// Twiddles of passes 1.. kept in registers for the whole segment loop.
+template <class T, int NC, int ORD> struct RegTwiddle {
+  cpx<T> p[FftPlan<NC>::NPASS][16];
+  __device__ __forceinline__ void init(const cpx<T>* __restrict__ tab, int t) {
+    init_pass<1>(tab, t);
+    init_pass<2>(tab, t);
+    if constexpr (FftPlan<NC>::NPASS == 4) init_pass<3>(tab, t);
+  }
+  template <int PASS> __device__ __forceinline__ void init_pass(const cpx<T>* __restrict__ tab, int t) {
+    constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS, NT = NC / 16;
+#pragma unroll
+    for (int m = 0; m < 16 / R; ++m) {
+      const int k = (t + NT * m) & (NS - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[PASS][m * R + r] = tab[(r * k) * (NC / (NS * R))];
+    }
+  }
+  template <int PASS> __device__ __forceinline__ cpx<T> get(int m, int r, int) const {
+    return p[PASS][m * PassInfo<NC, PASS, ORD>::R + r];
+  }
+};
+
+// Welch PSD of one (sample, detector) stretch x = background + o, by the
+// NC/16 threads t of a (sub-)block: K periodic-Hann segments of L = NC samples
+// at stride L/2.  Segments 2p and 2p+1 go through ONE complex FFT as real and
+// imaginary parts; since |A_k|^2 + |B_k|^2 = (|X_k|^2 + |X_{L-k}|^2)/2 for
+// X = FFT(a + i b), the accumulated |X|^2 is folded once at the end.
+template <class T, class ACC, int NC, int ORD>
+__device__ __forceinline__ void welch_item(int K, double norm, int t, const float* x, float* out, const cpx<T>* twtab,
+                                           T* sre, T* sim, bool active) {
+  constexpr int NT = NC / 16;
+  constexpr int LS = LdsSize<NC>::value;
+  static_assert(NC * sizeof(ACC) <= 2 * LS * sizeof(T), "fold buffer must fit in the FFT buffer");
+  T w[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const T sp = sinpi_t(T(t + NT * r) / T(NC));
+    w[r] = sp * sp;
+  }
+  RegTwiddle<T, NC, ORD> tw;
+  tw.init(twtab, t);
+  ACC acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = ACC(0);
+  // Pair p covers [p L, p L + 3L/2).  Its first half-segment was read by
+  // pair p-1; the next pair's 16 new values per thread are requested before
+  // the current transform so that their latency hides behind it.
+  const int npairs = (K + 1) / 2;
+  float cur[8], na[8], nb[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    cur[r] = x[t + NT * r];
+    na[r] = x[t + NT * (r + 8)];
+    nb[r] = (K > 1) ? x[NC / 2 + t + NT * (r + 8)] : 0.f;
+  }
+#pragma unroll 1
+  for (int p = 0; p < npairs; ++p) {
+    const bool has_b = (2 * p + 1) < K;
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float b_hi = has_b ? nb[r] : 0.f;
+      const float b_lo = has_b ? na[r] : 0.f;
+      v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), w[r] * T(b_lo)};
+      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), w[r + 8] * T(b_hi)};
+      cur[r] = nb[r];
+    }
+    if (p + 1 < npairs) {
+      const float* xn = x + int64_t(p + 1) * NC;
+      const bool nb_ok = (2 * (p + 1) + 1) < K;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        na[r] = xn[t + NT * (r + 8)];
+        nb[r] = nb_ok ? xn[NC / 2 + t + NT * (r + 8)] : 0.f;
+      }
+    }
+    if (p > 0) __syncthreads();
+    block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
+  }
+  __syncthreads();
+  ACC* fold = reinterpret_cast<ACC*>(sre);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = acc[e];
+  __syncthreads();
+  if (active) {
+    for (int k = t; k <= NC / 2; k += NT) {
+      const ACC s = (fold[k] + fold[(NC - k) & (NC - 1)]) * ACC(0.5);
+      const ACC ck = (k == 0 || k == NC / 2) ? ACC(1) : ACC(2);
+      out[k] = float(s * ck * ACC(norm));
+    }
+  }
+}
+
+}  // namespace gw

@@ -16,12 +16,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
 #include "gw_fft.hpp"
 #include "gw_physics.hpp"
 #include "gw_internal.hpp"
+#include "gw_items.hpp"
 #include "../../include/gwgen.h"
 
 using namespace gw;
@@ -32,6 +34,7 @@ namespace {
 struct SampleArgs {
   DevCfg cf;
   uint64_t seed, first;
+  const uint64_t* batch;  // device batch index (graph replays): first = *batch * B, or NULL
   int64_t B, span;
   double* params;
   int64_t* offset;
@@ -42,49 +45,11 @@ struct SampleArgs {
 };
 
 __global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
-#pragma clang fp contract(off)
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= a.B) return;
-  const uint64_t g = a.first + uint64_t(i);
-  const DevCfg& c = a.cf;
-  double u[11];
-#pragma unroll
-  for (int s = 0; s < 11; ++s) u[s] = philox_uniform(a.seed, g, uint32_t(s));
-  const double uo = philox_uniform(a.seed, g, 12u);
-  double p[12];
-  p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
-  p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
-  p[2] = c.chi[0] + u[2] * (c.chi[1] - c.chi[0]);
-  p[3] = c.chi[0] + u[3] * (c.chi[1] - c.chi[0]);
-  const double a3 = c.dl[0] * c.dl[0] * c.dl[0], b3 = c.dl[1] * c.dl[1] * c.dl[1];
-  p[4] = pow(a3 + u[4] * (b3 - a3), 1.0 / 3.0);
-  p[5] = acos(2.0 * u[5] - 1.0);
-  p[6] = 2.0 * kPi * u[6];
-  p[7] = asin(2.0 * u[7] - 1.0);
-  p[8] = kPi * u[8];
-  p[9] = 2.0 * kPi * u[9];
-  p[10] = c.T - 1.5 + u[10] * 1.0;
-  p[11] = 0.0;
-#pragma unroll
-  for (int r = 0; r < 12; ++r) a.params[r * a.B + i] = p[r];
-  a.offset[i] = int64_t(floor(uo * double(a.span)));
-  if (a.params_f32) {
-#pragma unroll
-    for (int r = 0; r < 12; ++r) a.params_f32[r * a.B + i] = float(p[r]);
-  }
-  if (a.status) {
-    const double eta = p[1] / ((1.0 + p[1]) * (1.0 + p[1]));
-    const double Ms = p[0] * pow(eta, -0.6) * kMsunSec;
-    const double f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
-    a.status[i] = f_cut > 0.5 * c.fs ? GW_STATUS_CUT_AT_NYQUIST : 0u;
-  }
-  if (a.wf) {
-    WfScalars w;
-    wf_setup(a.params, a.B, i, c, w);
-    a.wf[i] = w;
-    for (int d = 0; d < c.n_det; ++d)
-      a.dsc[i * c.n_det + d] = det_response(c.det[d], w.ra, w.dec, w.psi, w.tc);
-  }
+  const uint64_t first = a.batch ? *a.batch * uint64_t(a.B) : a.first;
+  draw_sample(a.cf, a.seed, first + uint64_t(i), i, a.B, a.span, 0.0, a.params, a.offset, a.params_f32, a.status,
+              a.wf, a.dsc);
 }
 
 // -------------------------------------------------------- plus / cross
@@ -162,218 +127,32 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   }
 }
 
-// ---------------------------------------- window kernels (FFT of length N)
-struct WinArgs {
-  DevCfg cf;
-  const float* src;       // strain [B][D][N] (SRC 0, 2) or background (SRC 1)
-  int64_t L_bg;
-  const float* bg;        // background for inject (SRC 2)
-  const int64_t* offset;
-  const double* params;
-  int64_t B;
-  const float* psd;       // [B][D][Fw]
-  float* out;
-  uint32_t* status;
-  const double* kcbrt;
-  const double* lnk3;
-  const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
-  const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
-  const WfScalars* wf;    // [B] (SRC 1, 3)
-  const DetScalars* dsc;  // [B][D] (SRC 1, 3)
-  const float* nodes;     // [B][2][1024] surrogate node values (SRC 3)
-  const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
-  float logmm_max;        // fallback threshold (SRC 3)
-};
-
-// Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
-constexpr int kSurrNodes = 1024;
-constexpr double kSurrLnMfLo = -6.2146080984221914;   // ln(2e-3)
-constexpr double kSurrDlog = 4.6051701859880914 / 1023.0;  // ln(0.2/2e-3)/(NN-1)
-
-// Whitening factor for window bin k in [0, N/2]; sets status bits.
-template <class T>
-__device__ __forceinline__ T whiten_gain(const WinArgs& a, const float* psd, int k, int NC, uint32_t& flag) {
-  if (k == 0 || k >= NC || k < a.cf.kmin) return T(0);
-  const int i = k >> a.cf.log2_ratio;
-  const T tt = T(k - (i << a.cf.log2_ratio)) * T(a.cf.inv_ratio);
-  const T S = (T(1) - tt) * T(psd[i]) + tt * T(psd[i + 1]);
-  if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
-  if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
-  return rsqrt_t(T(a.cf.fs) * S * T(0.5));
-}
-
-// Projected signal (DFT coefficients) at window bin k, generated in registers.
-template <class T, class TP, bool FULL>
-__device__ __forceinline__ cpx<T> signal_bin(const WinArgs& a, const WfScalars& w, T cpl, T cxx, double tauT, int k) {
-  if (k <= 0 || k < a.cf.kmin || k >= w.kend) return {T(0), T(0)};
-  const double kc = a.kcbrt[k], lk = a.lnk3[k];
-  TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
-  rev = frac1(rev);
-  T s, c;
-  sincos_rev(T(rev), &s, &c);
-  const T A = T(a.cf.fs) * wf_amplitude<T>(w, k, kc, a.cf.invT);
-  // fs A (cpl - i cxx)(c - i s)
-  return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
-}
-
-// Projected signal at window bin k from surrogate node values: binary64
-// Newtonian phase + interpolated phase residual (revolutions), amplitude
-// A_N(f_k) times the interpolated ratio.
-template <class T>
-__device__ __forceinline__ cpx<T> signal_bin_surr(const WinArgs& a, const WfScalars& w, const float* nd, T cpl, T cxx,
-                                                  double tauT, int k) {
-  if (k <= 0 || k < a.cf.kmin || k >= w.kend) return {T(0), T(0)};
-  const double kc = a.kcbrt[k], lk3 = a.lnk3[k];
-  // u = (ln(Ms k / T) - ln Mf_lo) / dlog, ln(Ms/T) = 3 ln v1 - ln pi
-  const float u = float((3.0 * w.lnv1 - 1.1447298858494002 + 3.0 * lk3 - kSurrLnMfLo) * (1.0 / kSurrDlog));
-  const float uc = fminf(fmaxf(u, 0.f), float(kSurrNodes - 1));
-  const int i = min(int(uc), kSurrNodes - 2);
-  const float tt = uc - float(i);
-  const float ratio = (1.f - tt) * nd[i] + tt * nd[i + 1];
-  const float dpsi = (1.f - tt) * nd[kSurrNodes + i] + tt * nd[kSurrNodes + i + 1];
-  const double v = w.v1 * kc;
-  const double iv = rcp_t(v);
-  const double iv2 = iv * iv;
-  double rev = w.a[0] * iv2 * iv2 * iv + double(dpsi) * (1.0 / (2.0 * kPi)) + w.pconst + double(k) * tauT;
-  rev = frac1(rev);
-  T sn, cs;
-  sincos_rev(T(rev), &sn, &cs);
-  const T A = T(a.cf.fs) * T(w.A0T) * rsqrt_t(T(kc)) * rcp_t(T(k)) * T(ratio);
-  return {A * (cpl * cs - cxx * sn), -A * (cpl * sn + cxx * cs)};
-}
-
-// SRC 0: whiten strain.  SRC 1: fused background + signal + whiten.
-// SRC 3: as SRC 1 with the signal from surrogate node values (plain model
-// where the predicted mismatch exceeds the threshold).
-// SRC 2: inject (out = bg window + irfft(hdet)); src is hdet [B][D][N/2+1].
 // Occupancy target: two workgroups per CU (VGPR budget 128 for 512 threads).
 template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
 
-template <class T, class TP, bool FULL, int NC, int SRC>
+template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
 __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a) {
-  constexpr int NT = NC / 16;
   constexpr int LS = LdsSize<NC>::value;
   __shared__ T lds[2 * LS];
   __shared__ uint32_t sflag;
-  T* sre = lds;
-  T* sim = lds + LS;
   const int t = threadIdx.x;
   const int64_t bd = blockIdx.x;
   const int D = a.cf.n_det;
   const int64_t b = bd / D;
   const int d = int(bd - b * D);
   const int N = 2 * NC;
-  const cpx<T>* twr = reinterpret_cast<const cpx<T>*>(a.twr);
-  PowTwiddle<T, NC> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
-  cpx<T> v[16];
-  uint32_t flag = 0;
   if (t == 0) sflag = 0;
-
-  if constexpr (SRC != 2) {
-    const float* x = (SRC == 0) ? a.src + bd * N : a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
-    static_assert(SRC >= 0 && SRC <= 3, "source");
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      float2 q;
-      __builtin_memcpy(&q, x + 2 * (t + NT * r), sizeof(q));
-      v[r] = {T(q.x), T(q.y)};
-    }
-    block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = lpad(fft_out_index<NC>(t, e));
-      sre[i] = v[e].x;
-      sim[i] = v[e].y;
-    }
-    __syncthreads();
-  }
-
-  const float* psd = a.psd + bd * a.cf.Fw;
-  T cpl = T(0), cxx = T(0);
-  double tauT = 0.0;
-  const WfScalars& wsh = a.wf[(SRC == 1 || SRC == 3) ? b : 0];
-  bool use_surr = false;
-  const float* nd = nullptr;
-  if constexpr (SRC == 3) {
-    use_surr = !(a.logmm[b] > a.logmm_max);
-    nd = a.nodes + b * 2 * kSurrNodes;
-    if (!use_surr && t == 0 && d == 0 && a.status) atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
-  }
-  if constexpr (SRC == 1 || SRC == 3) {
-    const DetScalars dsh = a.dsc[bd];
-    cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
-    cxx = T(dsh.fx * wsh.cosi);
-    tauT = dsh.tau * a.cf.invT;
-  }
-  const float2* hsrc = (SRC == 2) ? reinterpret_cast<const float2*>(a.src) + bd * (NC + 1) : nullptr;
-
-  // pairs (k, NC - k) for k in [0, NC/2]
-#pragma unroll 1
-  for (int i = 0; i <= 8; ++i) {
-    const int k = t + NT * i;
-    if (k > NC / 2) break;
-    const int km = NC - k;
-    const cpx<T> W = twr[k];  // exp(-2 pi i k / N)
-    cpx<T> Yk, Ym;
-    if constexpr (SRC == 2) {
-      const float2 h0 = hsrc[k], h1 = hsrc[km];
-      Yk = {T(h0.x), T(h0.y)};
-      Ym = {T(h1.x), T(h1.y)};
-      if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
-    } else {
-      const int ia = lpad(k), ib = lpad(km & (NC - 1));
-      const cpx<T> A = {sre[ia], sim[ia]};
-      const cpx<T> Bm = {sre[ib], sim[ib]};
-      const cpx<T> s = cadd(A, cconj(Bm));
-      const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
-      cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
-      cpx<T> Xm = {T(0.5) * (s.x - u.y), T(0.5) * (-s.y - u.x)};
-      if constexpr (SRC == 1) {
-        Xk = cadd(Xk, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, k));
-        if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, km));
-      } else if constexpr (SRC == 3) {
-        if (use_surr) {
-          Xk = cadd(Xk, signal_bin_surr<T>(a, wsh, nd, cpl, cxx, tauT, k));
-          if (km != k) Xm = cadd(Xm, signal_bin_surr<T>(a, wsh, nd, cpl, cxx, tauT, km));
-        } else {
-          Xk = cadd(Xk, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, k));
-          if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(a, wsh, cpl, cxx, tauT, km));
-        }
-      }
-      Yk = cscale(Xk, whiten_gain<T>(a, psd, k, NC, flag));
-      Ym = cscale(Xm, whiten_gain<T>(a, psd, km, NC, flag));
-      if (km == k) Ym = Yk;
-    }
-    // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
-    const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
-    const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
-    const int ia = lpad(k);
-    sre[ia] = p.x - q.y;
-    sim[ia] = p.y + q.x;
-    if (k != 0 && km != k) {
-      const int ib = lpad(km);
-      sre[ib] = p.x + q.y;
-      sim[ib] = -p.y + q.x;
-    }
-  }
-  __syncthreads();
-  block_fft<T, NC, +1, true>(v, sre, sim, t, tw);
-  float* o = a.out + bd * N;
-  const T sc = T(1) / T(NC);
+  const float* x = nullptr;
+  const float* hrow = nullptr;
   const float* nz = nullptr;
-  if constexpr (SRC == 2) nz = a.bg + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int n = fft_out_index<NC>(t, e);
-    float2 y = {float(v[e].x * sc), float(v[e].y * sc)};
-    if constexpr (SRC == 2) {
-      y.x += nz[2 * n];
-      y.y += nz[2 * n + 1];
-    }
-    reinterpret_cast<float2*>(o)[n] = y;
-  }
-  if (flag) atomicOr(&sflag, flag);
+  if constexpr (SRC == 0) x = a.src + bd * N;
+  else if constexpr (SRC == 2) {
+    hrow = a.src + bd * 2 * (NC + 1);
+    nz = a.bg + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
+  } else x = a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
+  window_item<T, TP, FULL, NC, SRC, ORD>(a.cf, a, t, b, d, x, hrow, nz, a.psd + bd * a.cf.Fw, a.out + bd * N,
+                                         reinterpret_cast<const cpx<T>*>(a.tw), reinterpret_cast<const cpx<T>*>(a.twr),
+                                         lds, lds + LS, true, &sflag);
   __syncthreads();
   if (t == 0 && sflag && a.status) atomicOr(a.status + b, sflag);
 }
@@ -389,111 +168,30 @@ struct WelchArgs {
   double norm;     // 1 / (K fs sum w^2)
 };
 
-// Twiddles of passes 1.. kept in registers for the whole segment loop.
-template <class T, int NC> struct RegTwiddle {
-  cpx<T> p[FftPlan<NC>::NPASS][16];
-  __device__ __forceinline__ void init(const cpx<T>* __restrict__ tab, int t) {
-    init_pass<1>(tab, t);
-    init_pass<2>(tab, t);
-    if constexpr (FftPlan<NC>::NPASS == 4) init_pass<3>(tab, t);
-  }
-  template <int PASS> __device__ __forceinline__ void init_pass(const cpx<T>* __restrict__ tab, int t) {
-    constexpr int R = PassInfo<NC, PASS>::R, NS = PassInfo<NC, PASS>::NS, NT = NC / 16;
-#pragma unroll
-    for (int m = 0; m < 16 / R; ++m) {
-      const int k = (t + NT * m) & (NS - 1);
-#pragma unroll
-      for (int r = 0; r < R; ++r) p[PASS][m * R + r] = tab[(r * k) * (NC / (NS * R))];
-    }
-  }
-  template <int PASS> __device__ __forceinline__ cpx<T> get(int m, int r, int) const {
-    return p[PASS][m * PassInfo<NC, PASS>::R + r];
-  }
-};
-
-// Per (sample, detector): K periodic-Hann segments of L samples at stride L/2
-// from [o, o + P).  Segments 2p and 2p+1 go through ONE complex FFT as real
-// and imaginary parts; since |A_k|^2 + |B_k|^2 = (|X_k|^2 + |X_{L-k}|^2)/2
-// for X = FFT(a + i b), the accumulated |X|^2 is folded once at the end.
-template <class T, class ACC, int NC>
+template <class T, class ACC, int NC, int ORD>
 __global__ __launch_bounds__(NC / 16) void k_welch(WelchArgs a) {
-  constexpr int NT = NC / 16;
   constexpr int LS = LdsSize<NC>::value;
-  static_assert(NC * sizeof(ACC) <= 2 * LS * sizeof(T), "fold buffer must fit in the FFT buffer");
   __shared__ T lds[2 * LS];
-  T* sre = lds;
-  T* sim = lds + LS;
-  const int t = threadIdx.x;
   const int64_t bd = blockIdx.x;
   const int D = a.cf.n_det;
   const int64_t b = bd / D;
   const int d = int(bd - b * D);
-  const float* x = a.bg + int64_t(d) * a.L_bg + a.offset[b];
-  T w[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const T sp = sinpi_t(T(t + NT * r) / T(NC));
-    w[r] = sp * sp;
-  }
-  RegTwiddle<T, NC> tw;
-  tw.init(reinterpret_cast<const cpx<T>*>(a.tw), t);
-  ACC acc[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = ACC(0);
-  // Pair p covers [p L, p L + 3L/2).  Its first half-segment was read by
-  // pair p-1; the next pair's 16 new values per thread are requested before
-  // the current transform so that their latency hides behind it.
-  const int K = a.cf.K;
-  const int npairs = (K + 1) / 2;
-  float cur[8], na[8], nb[8];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    cur[r] = x[t + NT * r];
-    na[r] = x[t + NT * (r + 8)];
-    nb[r] = (K > 1) ? x[NC / 2 + t + NT * (r + 8)] : 0.f;
-  }
-#pragma unroll 1
-  for (int p = 0; p < npairs; ++p) {
-    const bool has_b = (2 * p + 1) < K;
-    cpx<T> v[16];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const float b_hi = has_b ? nb[r] : 0.f;
-      const float b_lo = has_b ? na[r] : 0.f;
-      v[r] = {w[r] * T(cur[r]), w[r] * T(b_lo)};
-      v[r + 8] = {w[r + 8] * T(na[r]), w[r + 8] * T(b_hi)};
-      cur[r] = nb[r];
-    }
-    if (p + 1 < npairs) {
-      const float* xn = x + int64_t(p + 1) * NC;
-      const bool nb_ok = (2 * (p + 1) + 1) < K;
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        na[r] = xn[t + NT * (r + 8)];
-        nb[r] = nb_ok ? xn[NC / 2 + t + NT * (r + 8)] : 0.f;
-      }
-    }
-    if (p > 0) __syncthreads();
-    block_fft<T, NC, -1, false>(v, sre, sim, t, tw);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
-  }
-  __syncthreads();
-  ACC* fold = reinterpret_cast<ACC*>(lds);
-#pragma unroll
-  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC>(t, e)] = acc[e];
-  __syncthreads();
-  float* out = a.psd + bd * a.cf.Fw;
-  for (int k = t; k <= NC / 2; k += NT) {
-    const ACC s = (fold[k] + fold[(NC - k) & (NC - 1)]) * ACC(0.5);
-    const ACC ck = (k == 0 || k == NC / 2) ? ACC(1) : ACC(2);
-    out[k] = float(s * ck * ACC(a.norm));
-  }
+  welch_item<T, ACC, NC, ORD>(a.cf.K, a.norm, threadIdx.x, a.bg + int64_t(d) * a.L_bg + a.offset[b],
+                              a.psd + bd * a.cf.Fw, reinterpret_cast<const cpx<T>*>(a.tw), lds, lds + LS, true);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// batch counter of graph replays (vector stores, one lane)
+__global__ void k_set_u64(uint64_t* p, uint64_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_add_u64(uint64_t* p, uint64_t v) {
+  if (threadIdx.x == 0) *p += v;
 }
 
 }  // namespace
@@ -554,6 +252,57 @@ gw_status check_launch(gw_ctx* c, const char* what) {
 namespace gw {
 gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg) { return fail(c, s, msg); }
 gw_status ctx_check_launch(gw_ctx* c, const char* what) { return check_launch(c, what); }
+
+// Capture `enqueue` plus a batch-index increment into a graph on a private
+// stream; the device counter `batch` starts at `first`.
+gw_status capture_graph(const std::function<gw_status(hipStream_t)>& enqueue, uint64_t* batch, uint64_t first,
+                        gw_graph** out, std::string* why) {
+  if (hipMemcpy(batch, &first, sizeof(first), hipMemcpyHostToDevice) != hipSuccess) {
+    *why = "hipMemcpy batch counter";
+    return GW_EHIP;
+  }
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    *why = "hipStreamCreate";
+    return GW_EHIP;
+  }
+  gw_graph* g = new gw_graph();
+  g->batch = batch;
+  gw_status s = GW_OK;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    *why = "hipStreamBeginCapture";
+    s = GW_EHIP;
+  } else {
+    s = enqueue(st);
+    if (s == GW_OK) {
+      hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, st, batch, uint64_t(1));
+      if (hipGetLastError() != hipSuccess) {
+        *why = "k_add_u64";
+        s = GW_EHIP;
+      }
+    } else {
+      *why = "a launch failed during capture";
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s == GW_OK && e != hipSuccess) {
+      *why = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+      s = GW_EHIP;
+    }
+    g->graph = graph;
+    if (s == GW_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      *why = "hipGraphInstantiate";
+      s = GW_EHIP;
+    }
+  }
+  (void)hipStreamDestroy(st);
+  if (s != GW_OK) {
+    gw_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return GW_OK;
+}
 }  // namespace gw
 
 namespace {
@@ -637,24 +386,46 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   return GW_OK;
 }
 
+}  // namespace
+
+namespace gw {
+gw_status validate_config(const gw_config* g, DevCfg* dc, std::string* why) { return validate_cfg(g, dc, why); }
+}  // namespace gw
+
+namespace {
+
 static int64_t ws_params_bytes(int64_t B) { return ((B * 12 * 8 + 255) / 256) * 256; }
 static int64_t ws_offset_bytes(int64_t B) { return ((B * 8 + 255) / 256) * 256; }
 static int64_t ws_psd_bytes(const DevCfg& d, int64_t B) { return ((B * d.n_det * d.Fw * 4 + 255) / 256) * 256; }
 static int64_t ws_wf_bytes(int64_t B) { return ((B * int64_t(sizeof(WfScalars)) + 255) / 256) * 256; }
 static int64_t ws_det_bytes(const DevCfg& d, int64_t B) { return ((B * d.n_det * int64_t(sizeof(DetScalars)) + 255) / 256) * 256; }
+// 256 bytes after the per-sample arrays hold the graph batch counter
+static int64_t ws_counter_offset(const DevCfg& d, int64_t B) {
+  return ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(d, B) + ws_wf_bytes(B) + ws_det_bytes(d, B);
+}
 
-// dispatch a k_window instantiation on the window FFT size
-template <class T, class TP, bool FULL, int SRC>
-static void launch_window(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
+// dispatch a k_window instantiation on the window FFT size and radix order
+template <class T, class TP, bool FULL, int SRC, int ORD>
+static void launch_window_ord(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
   const int NC = d.N / 2;
   switch (NC) {
-    case 2048: hipLaunchKernelGGL((k_window<T, TP, FULL, 2048, SRC>), dim3(unsigned(blocks)), dim3(128), 0, stream, a); break;
-    case 4096: hipLaunchKernelGGL((k_window<T, TP, FULL, 4096, SRC>), dim3(unsigned(blocks)), dim3(256), 0, stream, a); break;
-    case 8192: hipLaunchKernelGGL((k_window<T, TP, FULL, 8192, SRC>), dim3(unsigned(blocks)), dim3(512), 0, stream, a); break;
+    case 2048: hipLaunchKernelGGL((k_window<T, TP, FULL, 2048, SRC, ORD>), dim3(unsigned(blocks)), dim3(128), 0, stream, a); break;
+    case 4096: hipLaunchKernelGGL((k_window<T, TP, FULL, 4096, SRC, 0>), dim3(unsigned(blocks)), dim3(256), 0, stream, a); break;
+    case 8192: hipLaunchKernelGGL((k_window<T, TP, FULL, 8192, SRC, ORD>), dim3(unsigned(blocks)), dim3(512), 0, stream, a); break;
     default:
       if constexpr (sizeof(T) == 4)
-        hipLaunchKernelGGL((k_window<T, TP, FULL, 16384, SRC>), dim3(unsigned(blocks)), dim3(1024), 0, stream, a);
+        hipLaunchKernelGGL((k_window<T, TP, FULL, 16384, SRC, ORD>), dim3(unsigned(blocks)), dim3(1024), 0, stream, a);
       break;
+  }
+}
+
+template <class T, class TP, bool FULL, int SRC>
+static void launch_window(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
+  if constexpr (sizeof(T) == 4) {
+    if (d.ord_win) launch_window_ord<T, TP, FULL, SRC, 1>(d, blocks, a, stream);
+    else launch_window_ord<T, TP, FULL, SRC, 0>(d, blocks, a, stream);
+  } else {
+    launch_window_ord<T, TP, FULL, SRC, 0>(d, blocks, a, stream);
   }
 }
 
@@ -678,8 +449,14 @@ static WinArgs win_args(gw_ctx* c) {
 
 template <class T, class ACC>
 static void launch_welch(const DevCfg& d, int64_t blocks, const WelchArgs& a, hipStream_t stream) {
-  if (d.L == 2048) hipLaunchKernelGGL((k_welch<T, ACC, 2048>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
-  else hipLaunchKernelGGL((k_welch<T, ACC, 4096>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+  if (d.L == 2048) {
+    if (sizeof(T) == 4 && d.ord_welch)
+      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 1>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 0>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+  } else {
+    hipLaunchKernelGGL((k_welch<T, ACC, 4096, 0>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+  }
 }
 
 static gw_status welch_launch(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset, int64_t B,
@@ -691,6 +468,68 @@ static gw_status welch_launch(gw_ctx* c, const float* bg, int64_t L_bg, const in
   else if (d.precision == 1) launch_welch<float, double>(d, blocks, a, stream);
   else launch_welch<double, double>(d, blocks, a, stream);
   return check_launch(c, "k_welch");
+}
+
+constexpr int kStageParams = 1, kStageWelch = 2, kStageWindow = 4, kStageAll = 7;
+constexpr int64_t kMaxBlocks = int64_t(1) << 31;
+
+// Host checks shared by the batch entry points (nothing is launched).
+static gw_status check_batch_args(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, const float* out,
+                                  const float* params_f32, const uint32_t* status, const void* workspace,
+                                  int64_t workspace_bytes) {
+  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
+  if (B == 0) return GW_OK;
+  if (!bg || !out || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(out) || !aligned16(workspace) || (params_f32 && !aligned16(params_f32)) ||
+      (status && !aligned4(status)))
+    return fail(c, GW_EINVAL, "misaligned pointer");
+  int64_t need = 0;
+  gw_workspace_size(c, B, &need);
+  if (workspace_bytes < need) return fail(c, GW_EINVAL, "workspace too small");
+  if (L_bg - c->dc.P - c->dc.N + 1 <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
+  return GW_OK;
+}
+
+// Queue the fused batch (prior draws, Welch PSDs, fused window kernel), or
+// the stages selected by `stages`.  `batch` (device, nullable) supplies the
+// batch index at run time for graph replays.
+static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, const uint64_t* batch, int64_t B,
+                               const float* bg, int64_t L_bg, float* out, float* params_f32, uint32_t* status,
+                               void* workspace, int stages, hipStream_t stream) {
+  const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
+  char* ws = static_cast<char*>(workspace);
+  double* params = reinterpret_cast<double*>(ws);
+  int64_t* offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
+  float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
+  WfScalars* wf = reinterpret_cast<WfScalars*>(ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B));
+  DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
+  gw_status s = GW_OK;
+  if (stages & kStageParams) {
+    SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), batch, B, span, params, offset, params_f32, status, wf, dsc};
+    hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
+    s = check_launch(c, "k_sample_params");
+    if (s != GW_OK) return s;
+  }
+  if (stages & kStageWelch) {
+    s = welch_launch(c, bg, L_bg, offset, B, psd, stream);
+    if (s != GW_OK) return s;
+  }
+  if (stages & kStageWindow) {
+    WinArgs a = win_args(c);
+    a.src = bg;
+    a.L_bg = L_bg;
+    a.offset = offset;
+    a.params = params;
+    a.B = B;
+    a.psd = psd;
+    a.out = out;
+    a.status = status;
+    a.wf = wf;
+    a.dsc = dsc;
+    launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
+    s = check_launch(c, "k_window<fused>");
+  }
+  return s;
 }
 
 }  // namespace
@@ -783,7 +622,7 @@ gw_status gw_query(const gw_ctx* c, int32_t key, int64_t* value) {
 
 gw_status gw_workspace_size(const gw_ctx* c, int64_t B, int64_t* bytes) {
   if (!c || !bytes || B < 0) return GW_EINVAL;
-  *bytes = ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B) + ws_wf_bytes(B) + ws_det_bytes(c->dc, B);
+  *bytes = ws_counter_offset(c->dc, B) + 256;
   return GW_OK;
 }
 
@@ -799,7 +638,7 @@ gw_status sample_params(gw_ctx* c, uint64_t seed, uint64_t first_index, int64_t 
   if (!aligned16(params) || !aligned16(offset)) return fail(c, GW_EINVAL, "params/offset not 16-byte aligned");
   const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
   if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
-  SampleArgs a{c->dc, seed, first_index, B, span, params, offset, nullptr, nullptr, nullptr, nullptr};
+  SampleArgs a{c->dc, seed, first_index, nullptr, B, span, params, offset, nullptr, nullptr, nullptr, nullptr};
   hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, a);
   return check_launch(c, "k_sample_params");
 }
@@ -832,8 +671,6 @@ gw_status project_detectors(gw_ctx* c, const double* params, const float* hp, co
   else hipLaunchKernelGGL((k_project<double>), grid, dim3(256), 0, stream, a);
   return check_launch(c, "k_project");
 }
-
-static const int64_t kMaxBlocks = int64_t(1) << 31;
 
 gw_status inject(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset, const float* hdet, int64_t B,
                  float* strain, hipStream_t stream) {
@@ -921,9 +758,9 @@ gw_status gw_generate_batch_surrogate(gw_ctx* c, gw_surrogate* sg, uint64_t seed
   float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
   WfScalars* wf = reinterpret_cast<WfScalars*>(ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B));
   DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
-  float* nodes = reinterpret_cast<float*>(reinterpret_cast<char*>(dsc) + ws_det_bytes(c->dc, B));
+  float* nodes = reinterpret_cast<float*>(ws + ws_counter_offset(c->dc, B) + 256);
   float* logmm = reinterpret_cast<float*>(reinterpret_cast<char*>(nodes) + ws_nodes_bytes(B));
-  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status, wf, dsc};
+  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), nullptr, B, span, params, offset, params_f32, status, wf, dsc};
   hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
   gw_status s = check_launch(c, "k_sample_params");
   if (s != GW_OK) return s;
@@ -953,43 +790,136 @@ gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int6
                             int64_t L_bg, float* out, float* params_f32, uint32_t* status, void* workspace,
                             int64_t workspace_bytes, hipStream_t stream) {
   GW_CHECK_CTX(c);
-  if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
-  if (B == 0) return GW_OK;
-  if (!bg || !out || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
-  if (!aligned4(bg) || !aligned16(out) || !aligned16(workspace) || (params_f32 && !aligned16(params_f32)) ||
-      (status && !aligned4(status)))
-    return fail(c, GW_EINVAL, "misaligned pointer");
-  int64_t need = 0;
-  gw_workspace_size(c, B, &need);
-  if (workspace_bytes < need) return fail(c, GW_EINVAL, "workspace too small");
-  const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
-  if (span <= 0) return fail(c, GW_EINVAL, "L_bg < P + N");
+  gw_status s = check_batch_args(c, B, bg, L_bg, out, params_f32, status, workspace, workspace_bytes);
+  if (s != GW_OK || B == 0) return s;
   if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
-  char* ws = static_cast<char*>(workspace);
-  double* params = reinterpret_cast<double*>(ws);
-  int64_t* offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
-  float* psd = reinterpret_cast<float*>(ws + ws_params_bytes(B) + ws_offset_bytes(B));
-  WfScalars* wf = reinterpret_cast<WfScalars*>(ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B));
-  DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
-  SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), B, span, params, offset, params_f32, status, wf, dsc};
-  hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
-  gw_status s = check_launch(c, "k_sample_params");
+  return enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out, params_f32, status, workspace, kStageAll,
+                       stream);
+}
+
+gw_status gw_graph_create(gw_ctx* c, uint64_t seed, uint64_t first_batch, int64_t B, const float* bg, int64_t L_bg,
+                          float* out, float* params_f32, uint32_t* status, void* workspace, int64_t workspace_bytes,
+                          gw_graph** graph) {
+  GW_CHECK_CTX(c);
+  if (!graph) return fail(c, GW_EINVAL, "graph is NULL");
+  *graph = nullptr;
+  gw_status s = check_batch_args(c, B, bg, L_bg, out, params_f32, status, workspace, workspace_bytes);
   if (s != GW_OK) return s;
-  s = welch_launch(c, bg, L_bg, offset, B, psd, stream);
+  if (B == 0) return fail(c, GW_EINVAL, "B must be positive");
+  uint64_t* batch = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + ws_counter_offset(c->dc, B));
+  std::string why;
+  s = capture_graph(
+      [&](hipStream_t st) {
+        return enqueue_batch(c, seed, 0, batch, B, bg, L_bg, out, params_f32, status, workspace, kStageAll, st);
+      },
+      batch, first_batch, graph, &why);
+  if (s != GW_OK) return fail(c, s, why);
+  return GW_OK;
+}
+
+gw_status gw_graph_launch(gw_graph* g, hipStream_t stream) {
+  if (!g) return GW_EINVAL;
+  const hipError_t e = hipGraphLaunch(g->exec, stream);
+  if (e != hipSuccess) {
+    g->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+    return GW_EHIP;
+  }
+  return GW_OK;
+}
+
+gw_status gw_graph_set_batch(gw_graph* g, uint64_t batch_index, hipStream_t stream) {
+  if (!g) return GW_EINVAL;
+  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, stream, g->batch, batch_index);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g->err = std::string("k_set_u64: ") + hipGetErrorString(e);
+    return GW_EHIP;
+  }
+  return GW_OK;
+}
+
+const char* gw_graph_last_error(const gw_graph* g) { return g ? g->err.c_str() : "graph is NULL"; }
+
+gw_status gw_graph_destroy(gw_graph* g) {
+  if (!g) return GW_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return GW_OK;
+}
+
+gw_status gw_set_tuning(gw_ctx* c, int32_t key, int64_t value) {
+  GW_CHECK_CTX(c);
+  if (value < 0 || value > 1) return fail(c, GW_EINVAL, "tuning value must be 0 or 1");
+  if (c->dc.precision == 2 && value != 0) return fail(c, GW_EUNSUPPORTED, "binary64 kernels have one radix order");
+  switch (key) {
+    case GW_TUNE_ORD_WINDOW: c->dc.ord_win = int(value); break;
+    case GW_TUNE_ORD_WELCH: c->dc.ord_welch = int(value); break;
+    default: return fail(c, GW_EINVAL, "unknown tuning key");
+  }
+  return GW_OK;
+}
+
+gw_status gw_get_tuning(const gw_ctx* c, int32_t key, int64_t* value) {
+  if (!c || !value) return GW_EINVAL;
+  switch (key) {
+    case GW_TUNE_ORD_WINDOW: *value = c->dc.ord_win; break;
+    case GW_TUNE_ORD_WELCH: *value = c->dc.ord_welch; break;
+    default: return GW_EINVAL;
+  }
+  return GW_OK;
+}
+
+gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float* out, void* workspace,
+                      int64_t workspace_bytes, int32_t reps, double* report) {
+  GW_CHECK_CTX(c);
+  gw_status s = check_batch_args(c, B, bg, L_bg, out, nullptr, nullptr, workspace, workspace_bytes);
   if (s != GW_OK) return s;
-  WinArgs a = win_args(c);
-  a.src = bg;
-  a.L_bg = L_bg;
-  a.offset = offset;
-  a.params = params;
-  a.B = B;
-  a.psd = psd;
-  a.out = out;
-  a.status = status;
-  a.wf = wf;
-  a.dsc = dsc;
-  launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
-  return check_launch(c, "k_window<fused>");
+  if (B == 0 || reps < 1 || reps > 1000) return fail(c, GW_EINVAL, "need B > 0 and 1 <= reps <= 1000");
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(c, GW_EHIP, "hipStreamCreate");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms[2][2] = {{0, 0}, {0, 0}};  // [stage: Welch, window][radix order]
+  const int n_ord = c->dc.precision == 2 ? 1 : 2;
+  const int saved[2] = {c->dc.ord_welch, c->dc.ord_win};
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    s = fail(c, GW_EHIP, "hipEventCreate");
+  } else {
+    s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, kStageAll, st);
+    for (int stage = 0; stage < 2 && s == GW_OK; ++stage) {
+      for (int o = 0; o < n_ord && s == GW_OK; ++o) {
+        if (stage == 0) c->dc.ord_welch = o; else c->dc.ord_win = o;
+        const int mask = stage == 0 ? kStageWelch : kStageWindow;
+        s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);  // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == GW_OK; ++r)
+          s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { s = fail(c, GW_EHIP, "hipEventSynchronize"); break; }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        ms[stage][o] = double(t) / reps;
+      }
+    }
+  }
+  if (s == GW_OK) {
+    c->dc.ord_welch = (n_ord == 2 && ms[0][1] < ms[0][0]) ? 1 : 0;
+    c->dc.ord_win = (n_ord == 2 && ms[1][1] < ms[1][0]) ? 1 : 0;
+    if (report) {
+      report[0] = ms[0][0];
+      report[1] = n_ord == 2 ? ms[0][1] : ms[0][0];
+      report[2] = ms[1][0];
+      report[3] = n_ord == 2 ? ms[1][1] : ms[1][0];
+    }
+  } else {
+    c->dc.ord_welch = saved[0];
+    c->dc.ord_win = saved[1];
+  }
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  return s;
 }
 
 }  // extern "C"

@@ -32,7 +32,17 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_surrogate_gradients", "gw_surrogate_train_step", "gw_surrogate_hidden",
            "gw_surrogate_set_head", "gw_surrogate_fit_head", "gw_surrogate_nodes",
            "gw_surrogate_waveform", "gw_mismatch", "gw_surrogate_save", "gw_surrogate_load",
-           "gw_surrogate_set_state", "gw_workspace_size_surrogate", "gw_generate_batch_surrogate")
+           "gw_surrogate_set_state", "gw_workspace_size_surrogate", "gw_generate_batch_surrogate",
+           "gw_graph_create", "gw_graph_launch", "gw_graph_set_batch", "gw_graph_last_error",
+           "gw_graph_destroy", "gw_set_tuning", "gw_get_tuning", "gw_autotune",
+           "gw_ragged_create", "gw_ragged_destroy", "gw_ragged_last_error", "gw_ragged_query",
+           "gw_ragged_offsets", "gw_generate_ragged", "gw_ragged_graph_create",
+           "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune")
+
+TUNE_ORD_WINDOW, TUNE_ORD_WELCH = 1, 2
+RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH = 1, 2, 3, 4
+(RQ_B, RQ_OUT_FLOATS, RQ_PSD_FLOATS, RQ_WORKSPACE, RQ_PSD_OFFSET, RQ_NCLASSES) = range(6)
+RAGGED_MAX_CLASSES = 8
 
 
 class GWConfig(ctypes.Structure):
@@ -97,6 +107,24 @@ def lib():
             "gw_workspace_size_surrogate": ([vp, i64, ctypes.POINTER(i64)], i32),
             "gw_generate_batch_surrogate": ([vp, vp, u64, u64, i64, vp, i64, vp, vp, vp, ctypes.c_float, vp,
                                              i64, vp], i32),
+            "gw_graph_create": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp, i64, ctypes.POINTER(vp)], i32),
+            "gw_graph_launch": ([vp, vp], i32),
+            "gw_graph_set_batch": ([vp, u64, vp], i32),
+            "gw_graph_last_error": ([vp], ctypes.c_char_p),
+            "gw_graph_destroy": ([vp], i32),
+            "gw_set_tuning": ([vp, i32, i64], i32),
+            "gw_get_tuning": ([vp, i32, ctypes.POINTER(i64)], i32),
+            "gw_autotune": ([vp, i64, vp, i64, vp, vp, i64, i32, vp], i32),
+            "gw_ragged_create": ([ctypes.POINTER(GWConfig), i32, vp, i64, ctypes.POINTER(vp)], i32),
+            "gw_ragged_destroy": ([vp], i32),
+            "gw_ragged_last_error": ([vp], ctypes.c_char_p),
+            "gw_ragged_query": ([vp, i32, ctypes.POINTER(i64)], i32),
+            "gw_ragged_offsets": ([vp, vp, vp], i32),
+            "gw_generate_ragged": ([vp, u64, u64, vp, vp, vp, vp, vp, vp, i64, vp], i32),
+            "gw_ragged_graph_create": ([vp, u64, u64, vp, vp, vp, vp, vp, vp, i64, ctypes.POINTER(vp)], i32),
+            "gw_ragged_set_tuning": ([vp, i32, i64], i32),
+            "gw_ragged_get_tuning": ([vp, i32, ctypes.POINTER(i64)], i32),
+            "gw_ragged_autotune": ([vp, vp, vp, vp, vp, i64, i32, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -305,3 +333,204 @@ class Generator:
         import torch
         n = self.workspace_size(B)
         return torch.empty((n + 7) // 8, dtype=torch.float64, device=device)
+
+    # -- graphs and tuning ------------------------------------------------
+    def graph(self, seed, first_batch, B, bg, out, workspace, params_f32=None, status=None):
+        """Captured gw_generate_batch; each launch advances the batch index."""
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        h = ctypes.c_void_p()
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_graph_create(self._h, int(seed), int(first_batch), int(B), _ptr(bg), bg.shape[1],
+                                          _ptr(out), _ptr(params_f32), _ptr(status), _ptr(workspace), nbytes,
+                                          ctypes.byref(h)), "gw_graph_create")
+        return Graph(h, keep=(bg, out, workspace, params_f32, status))
+
+    def set_tuning(self, key, value):
+        self._check(lib().gw_set_tuning(self._h, int(key), int(value)), "gw_set_tuning")
+
+    def get_tuning(self, key):
+        v = ctypes.c_int64()
+        self._check(lib().gw_get_tuning(self._h, int(key), ctypes.byref(v)), "gw_get_tuning")
+        return v.value
+
+    def autotune(self, B, bg, out, workspace, reps=5):
+        """Pick the radix orders; returns the mean ms per variant."""
+        import torch
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
+        rep = (ctypes.c_double * 4)()
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_autotune(self._h, int(B), _ptr(bg), bg.shape[1], _ptr(out), _ptr(workspace), nbytes,
+                                      int(reps), ctypes.cast(rep, ctypes.c_void_p)), "gw_autotune")
+        return {"welch_ord0": rep[0], "welch_ord1": rep[1], "window_ord0": rep[2], "window_ord1": rep[3]}
+
+
+class Graph:
+    """A captured batch pipeline (gw_graph)."""
+
+    def __init__(self, h, keep):
+        self._h = h
+        self._keep = keep  # the buffers the graph was captured with
+
+    def launch(self):
+        s = lib().gw_graph_launch(self._h, _stream())
+        if s != GW_OK:
+            raise GWError("gw_graph_launch: %s" % lib().gw_graph_last_error(self._h).decode())
+
+    def set_batch(self, batch_index):
+        s = lib().gw_graph_set_batch(self._h, int(batch_index), _stream())
+        if s != GW_OK:
+            raise GWError("gw_graph_set_batch: %s" % lib().gw_graph_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gw_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ragged:
+    """A gw_ragged plan: B signal slots, each of one size class."""
+
+    def __init__(self, classes, cls):
+        import numpy as np
+        self.classes = [dict(c) for c in classes]
+        n = len(self.classes)
+        if not 1 <= n <= RAGGED_MAX_CLASSES:
+            raise ValueError("1..%d classes" % RAGGED_MAX_CLASSES)
+        self.cls = np.ascontiguousarray(cls, dtype=np.int32)
+        self.B = int(self.cls.shape[0])
+        arr = (GWConfig * n)(*[make_config(c) for c in self.classes])
+        self._cfgs = arr
+        h = ctypes.c_void_p()
+        s = lib().gw_ragged_create(arr, n, self.cls.ctypes.data_as(ctypes.c_void_p), self.B, ctypes.byref(h))
+        if s != GW_OK:
+            raise GWError("gw_ragged_create failed: %s" % lib().gw_strerror(s).decode())
+        self._h = h
+        self.D = len(self.classes[0]["det_ids"])
+        self.out_floats = self._query(RQ_OUT_FLOATS)
+        self.psd_floats = self._query(RQ_PSD_FLOATS)
+        self.workspace_bytes = self._query(RQ_WORKSPACE)
+        self.psd_byte_offset = self._query(RQ_PSD_OFFSET)
+        self.out_offset = np.zeros(self.B + 1, dtype=np.int64)
+        self.psd_offset = np.zeros(self.B + 1, dtype=np.int64)
+        s = lib().gw_ragged_offsets(self._h, self.out_offset.ctypes.data_as(ctypes.c_void_p),
+                                    self.psd_offset.ctypes.data_as(ctypes.c_void_p))
+        self._check(s, "gw_ragged_offsets")
+
+    def _check(self, s, what):
+        if s != GW_OK:
+            msg = lib().gw_ragged_last_error(self._h).decode()
+            raise GWError("%s: %s (%s)" % (what, lib().gw_strerror(s).decode(), msg))
+
+    def _query(self, key):
+        v = ctypes.c_int64()
+        self._check(lib().gw_ragged_query(self._h, key, ctypes.byref(v)), "gw_ragged_query")
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gw_ragged_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.empty((self.workspace_bytes + 7) // 8, dtype=torch.float64, device=device)
+
+    def alloc_out(self, device="cuda"):
+        import torch
+        return torch.empty(self.out_floats, dtype=torch.float32, device=device)
+
+    def _bg_arrays(self, bgs):
+        """bgs: list (one per class) of float32 device tensors [D][L_bg]."""
+        import torch
+        if len(bgs) != len(self.classes):
+            raise ValueError("one background per class")
+        for b in bgs:
+            _want(b, torch.float32, (self.D, b.shape[1]), "bg")
+        n = len(bgs)
+        ptrs = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bgs])
+        lens = (ctypes.c_int64 * n)(*[b.shape[1] for b in bgs])
+        return ptrs, lens
+
+    def _common(self, out, workspace, params_f32, status):
+        import torch
+        _want(out, torch.float32, (self.out_floats,), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, self.B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (self.B,), "status")
+        if workspace.device.type != "cuda" or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous device tensor")
+        return workspace.numel() * workspace.element_size()
+
+    def generate(self, seed, batch_index, bgs, out, workspace, params_f32=None, status=None):
+        nbytes = self._common(out, workspace, params_f32, status)
+        ptrs, lens = self._bg_arrays(bgs)
+        self._check(lib().gw_generate_ragged(self._h, int(seed), int(batch_index), ctypes.cast(ptrs, ctypes.c_void_p),
+                                             ctypes.cast(lens, ctypes.c_void_p), _ptr(out), _ptr(params_f32),
+                                             _ptr(status), _ptr(workspace), nbytes, _stream()),
+                    "gw_generate_ragged")
+
+    def graph(self, seed, first_batch, bgs, out, workspace, params_f32=None, status=None):
+        nbytes = self._common(out, workspace, params_f32, status)
+        ptrs, lens = self._bg_arrays(bgs)
+        h = ctypes.c_void_p()
+        self._check(lib().gw_ragged_graph_create(self._h, int(seed), int(first_batch),
+                                                 ctypes.cast(ptrs, ctypes.c_void_p),
+                                                 ctypes.cast(lens, ctypes.c_void_p), _ptr(out), _ptr(params_f32),
+                                                 _ptr(status), _ptr(workspace), nbytes, ctypes.byref(h)),
+                    "gw_ragged_graph_create")
+        return Graph(h, keep=(tuple(bgs), out, workspace, params_f32, status))
+
+    def set_tuning(self, key, value):
+        self._check(lib().gw_ragged_set_tuning(self._h, int(key), int(value)), "gw_ragged_set_tuning")
+
+    def get_tuning(self, key):
+        v = ctypes.c_int64()
+        self._check(lib().gw_ragged_get_tuning(self._h, int(key), ctypes.byref(v)), "gw_ragged_get_tuning")
+        return v.value
+
+    def autotune(self, bgs, out, workspace, reps=3):
+        """Pick radix orders and the Welch grid; returns the timing table [ms]."""
+        nbytes = self._common(out, workspace, None, None)
+        ptrs, lens = self._bg_arrays(bgs)
+        rep = (ctypes.c_double * 8)()
+        self._check(lib().gw_ragged_autotune(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
+                                             ctypes.cast(lens, ctypes.c_void_p), _ptr(out), _ptr(workspace),
+                                             nbytes, int(reps), ctypes.cast(rep, ctypes.c_void_p)),
+                    "gw_ragged_autotune")
+        return {"welch": {(o, g): rep[o * 3 + i] for o in (0, 1) for i, g in enumerate((1, 2, 4))},
+                "window": {0: rep[6], 1: rep[7]}}
+
+    def signal(self, out, i):
+        """View [D][N_i] of signal slot i in the flat output."""
+        a, b = int(self.out_offset[i]), int(self.out_offset[i + 1])
+        return out[a:b].view(self.D, (b - a) // self.D)
+
+    def workspace_views(self, workspace):
+        """(params float64 [12][B], offsets int64 [B], flat PSD float32) in the workspace."""
+        import torch
+        B = self.B
+        pb = ((B * 12 * 8 + 255) // 256) * 256
+        raw = workspace.view(torch.uint8)
+        params = raw[:B * 12 * 8].view(torch.float64).view(N_PARAMS, B)
+        offs = raw[pb:pb + B * 8].view(torch.int64)
+        psd = raw[self.psd_byte_offset:self.psd_byte_offset + 4 * self.psd_floats].view(torch.float32)
+        return params, offs, psd

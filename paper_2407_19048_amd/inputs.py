@@ -46,6 +46,35 @@ CONFIGS["precision_study"] = dict(CONFIGS["paper_scale"], batch=8192)
 CONFIGS["surrogate"] = dict(CONFIGS["paper_scale"], batch=8192)
 
 
+# Uneven batches: 16384 signals, H1+L1+V1, durations {4, 8, 16} s x sample
+# rates {1024, 2048} Hz (six classes), Welch over the 64 s before each window
+# with 2 s segments at 50 % overlap; f_min 30 Hz for 4 s windows, else 20 Hz;
+# priors of the paper-scale workload.  Each slot's class is drawn uniformly
+# (seeded).
+RAGGED_RATES = (1024.0, 2048.0)
+RAGGED_DURATIONS = (4.0, 8.0, 16.0)
+RAGGED_BATCH = 16384
+
+
+def ragged_classes(precision=1):
+    """The six class configurations, ordered (fs, T) = (1024, 4), (1024, 8),
+    (1024, 16), (2048, 4), (2048, 8), (2048, 16)."""
+    out = []
+    for fs in RAGGED_RATES:
+        for T in RAGGED_DURATIONS:
+            c = dict(CONFIGS["paper_scale"], fs=fs, t_window=T, psd_length=64.0, fftlen=2.0, overlap=1.0,
+                     f_min=30.0 if T == 4.0 else 20.0, precision=precision)
+            c["log2_bg"] = 27 if fs == 2048.0 else 26
+            out.append(c)
+    return out
+
+
+def ragged_assignment(B, n_classes=6, seed=11):
+    """Class index per slot, uniform over the classes (numpy PCG64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(0, n_classes, size=B).astype(np.int32)
+
+
 def config(name, **overrides):
     c = dict(CONFIGS[name])
     c.update(overrides)
