@@ -325,6 +325,7 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
   // pair p-1; the next pair's 16 new values per thread are requested before
   // the current transform so that their latency hides behind it.
   const int npairs = (K + 1) / 2;
+  const int nfull = K / 2;  // pairs holding two segments; with K odd the last pair holds one
   float cur[8], na[8], nb[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -333,27 +334,39 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
     nb[r] = (K > 1) ? x[NC / 2 + t + NT * (r + 8)] : 0.f;
   }
 #pragma unroll 1
-  for (int p = 0; p < npairs; ++p) {
-    const bool has_b = (2 * p + 1) < K;
+  for (int p = 0; p < nfull; ++p) {
     cpx<T> v[16];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const float b_hi = has_b ? nb[r] : 0.f;
-      const float b_lo = has_b ? na[r] : 0.f;
-      v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), w[r] * T(b_lo)};
-      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), w[r + 8] * T(b_hi)};
+      v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), w[r] * T(na[r])};
+      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), w[r + 8] * T(nb[r])};
       cur[r] = nb[r];
     }
-    if (p + 1 < npairs) {
-      const float* xn = x + int64_t(p + 1) * NC;
-      const bool nb_ok = (2 * (p + 1) + 1) < K;
+    const float* xn = x + int64_t(p + 1) * NC;
+    if (p + 1 < nfull) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         na[r] = xn[t + NT * (r + 8)];
-        nb[r] = nb_ok ? xn[NC / 2 + t + NT * (r + 8)] : 0.f;
+        nb[r] = xn[NC / 2 + t + NT * (r + 8)];
       }
+    } else if (p + 1 < npairs) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) na[r] = xn[t + NT * (r + 8)];
     }
     if (p > 0) __syncthreads();
+    block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
+  }
+  if (nfull < npairs) {
+    // the last segment alone: real input, zero imaginary part
+    cpx<T> v[16];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), T(0)};
+      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), T(0)};
+    }
+    if (nfull > 0) __syncthreads();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);

@@ -104,6 +104,7 @@ struct WfScalars {
   double mr_b0, mr_b1;  // merger-ringdown phase in revolutions: b0 + b1 f + atan(x)/(2 pi)
   double f_rd, inv_fdamp;
   double At, Ard, ft, fdamp2;
+  double Apl;           // At (f_t T)^(2/3): power-law amplitude Apl k^(-2/3) between f_t and f_RD
   int kend, kt, krd;    // band end; first bins with f >= f_t and f >= f_RD
   int cut_nyquist;
   double cosi, tc, ra, dec, psi;
@@ -194,7 +195,7 @@ __device__ __forceinline__ void wf_setup(const double* __restrict__ params, int6
     w.kt = w.kend;
     w.krd = w.kend;
     w.mr_b0 = w.mr_b1 = w.f_rd = w.inv_fdamp = 0.0;
-    w.At = w.Ard = w.ft = w.fdamp2 = 0.0;
+    w.At = w.Ard = w.ft = w.fdamp2 = w.Apl = 0.0;
   } else {
     f_cut = 0.2 / Ms;
     w.kend = first_bin_at_or_above(f_cut, cf.T, knyq);
@@ -226,6 +227,7 @@ __device__ __forceinline__ void wf_setup(const double* __restrict__ params, int6
     w.Ard = At * pow(f_rd / f_t, -2.0 / 3.0);
     w.ft = f_t;
     w.fdamp2 = f_damp * f_damp;
+    w.Apl = At * pow(f_t * cf.T, 2.0 / 3.0);
     w.kt = min(first_bin_at_or_above(f_t, cf.T, knyq), w.kend);
     w.krd = min(first_bin_at_or_above(f_rd, cf.T, knyq), w.kend);
   }
@@ -257,13 +259,17 @@ __device__ __forceinline__ TP wf_phase_rev(const WfScalars& w, int k, double kcb
   else return TP(w.mr_b0) + TP(w.mr_b1) * TP(f) + TP(atanf(float(x)) * float(1.0 / (2.0 * kPi)));
 }
 
+// Amplitude at bin k: A0T k^(-7/6) below f_t, At (f/f_t)^(-2/3) =
+// Apl k^(-2/3) up to f_RD (both from the k^(1/3) table), then the Lorentzian.
 template <class TA>
 __device__ __forceinline__ TA wf_amplitude(const WfScalars& w, int k, double kcbrt, double invT) {
   if (k < w.kt) return TA(w.A0T) * rsqrt_t(TA(kcbrt)) * rcp_t(TA(k));
-  const TA f = TA(double(k) * invT);
-  if (k < w.krd) return TA(w.At) * pow_t(f / TA(w.ft), TA(-2.0) / TA(3.0));
-  const TA d = f - TA(w.f_rd);
-  return TA(w.Ard) * TA(w.fdamp2) / (d * d + TA(w.fdamp2));
+  if (k < w.krd) {
+    const TA kc = TA(kcbrt);
+    return TA(w.Apl) * rcp_t(kc * kc);
+  }
+  const TA d = TA(double(k) * invT) - TA(w.f_rd);
+  return TA(w.Ard) * TA(w.fdamp2) * rcp_t(d * d + TA(w.fdamp2));
 }
 
 // -------------------------------------------------------- detector response
