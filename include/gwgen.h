@@ -227,16 +227,20 @@ gw_status gw_graph_destroy(gw_graph* graph);
 
 /* Kernel variants.  GW_TUNE_ORD_*: 0 puts the FFT's small radix pass last,
  * 1 puts it first (same result up to rounding; which is faster depends on
- * the size).  Binary64 kernels (precision 2) have order 0 only. */
+ * the size).  GW_TUNE_OCC_WELCH: 2 or 3 waves per SIMD for the Welch kernel
+ * (3 trades spilled twiddles for occupancy).  Binary64 kernels (precision 2)
+ * have one variant. */
 #define GW_TUNE_ORD_WINDOW 1
 #define GW_TUNE_ORD_WELCH  2
+#define GW_TUNE_OCC_WELCH  3
 gw_status gw_set_tuning(gw_ctx* ctx, int32_t key, int64_t value);
 gw_status gw_get_tuning(const gw_ctx* ctx, int32_t key, int64_t* value);
-/* Autotuner: runs one batch of size B, then times the Welch and the fused
- * window kernel under each radix order over `reps` launches on a private
- * stream (synchronous) and keeps the faster of each.  report (host double
- * [4], nullable) receives the mean ms of Welch order 0, Welch order 1,
- * window order 0, window order 1.  Overwrites out and workspace. */
+/* Autotuner: runs one batch of size B, then times the Welch kernel under
+ * each (radix order, occupancy) and the fused window kernel under each radix
+ * order, over `reps` launches each on a private stream (synchronous), and
+ * keeps the fastest.  report (host double [6], nullable) receives the mean ms
+ * of Welch (order 0, occ 2), (1, 2), (0, 3), (1, 3), then window order 0 and
+ * 1.  Overwrites out and workspace. */
 gw_status gw_autotune(gw_ctx* ctx, int64_t B, const float* bg, int64_t L_bg,
                       float* out, void* workspace, int64_t workspace_bytes,
                       int32_t reps, double* report);

@@ -68,6 +68,7 @@ struct DetGeom {
 struct DevCfg {
   int n_det, N, F, P, L, S, K, Fw, ratio, log2_ratio, approximant, precision, kmin;
   int ord_win, ord_welch;  // FFT radix order of the window and Welch kernels (0: small radix last)
+  int occ_welch;           // waves per SIMD the Welch kernel is compiled for (2 or 3)
   double fs, T, invT, f_min, inv_ratio;
   double mc[2], q[2], chi[2], dl[2];
   DetGeom det[4];

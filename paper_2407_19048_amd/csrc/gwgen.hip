@@ -13,6 +13,7 @@
 //                                             the signal in registers (fused)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -127,7 +128,8 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   }
 }
 
-// Occupancy target: two workgroups per CU (VGPR budget 128 for 512 threads).
+// Second launch bound: minimum waves per SIMD (clamped to what LDS allows);
+// 4 waves per SIMD gives a budget of 128 VGPRs.
 template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
 
 template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
@@ -168,8 +170,10 @@ struct WelchArgs {
   double norm;     // 1 / (K fs sum w^2)
 };
 
-template <class T, class ACC, int NC, int ORD>
-__global__ __launch_bounds__(NC / 16) void k_welch(WelchArgs a) {
+// OCC: waves per SIMD the register allocation must allow (2, or 3 with the
+// loop-invariant twiddles partly spilled and reloaded per segment pair).
+template <class T, class ACC, int NC, int ORD, int OCC>
+__global__ __launch_bounds__(NC / 16, OCC) void k_welch(WelchArgs a) {
   constexpr int LS = LdsSize<NC>::value;
   __shared__ T lds[2 * LS];
   const int64_t bd = blockIdx.x;
@@ -381,6 +385,7 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   while (k > 0 && double(k - 1) / g->t_window >= g->f_min) --k;
   while (double(k) / g->t_window < g->f_min) ++k;
   c.kmin = k;
+  c.occ_welch = 2;
   for (int d = 0; d < g->n_det; ++d) c.det[d] = make_detector(g->det_id[d]);
   *dc = c;
   return GW_OK;
@@ -447,15 +452,27 @@ static WinArgs win_args(gw_ctx* c) {
   return a;
 }
 
+template <class T, class ACC, int OCC>
+static void launch_welch_occ(const DevCfg& d, int64_t blocks, const WelchArgs& a, hipStream_t stream) {
+  if (d.L == 2048) {
+    if (d.ord_welch)
+      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 1, OCC>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+    else
+      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 0, OCC>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+  } else {
+    hipLaunchKernelGGL((k_welch<T, ACC, 4096, 0, OCC>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+  }
+}
+
 template <class T, class ACC>
 static void launch_welch(const DevCfg& d, int64_t blocks, const WelchArgs& a, hipStream_t stream) {
-  if (d.L == 2048) {
-    if (sizeof(T) == 4 && d.ord_welch)
-      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 1>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
-    else
-      hipLaunchKernelGGL((k_welch<T, ACC, 2048, 0>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+  if constexpr (sizeof(T) == 4) {
+    if (d.occ_welch == 3) launch_welch_occ<T, ACC, 3>(d, blocks, a, stream);
+    else launch_welch_occ<T, ACC, 2>(d, blocks, a, stream);
   } else {
-    hipLaunchKernelGGL((k_welch<T, ACC, 4096, 0>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+    // binary64: one radix order, occupancy as the registers allow
+    if (d.L == 2048) hipLaunchKernelGGL((k_welch<T, ACC, 2048, 0, 1>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
+    else hipLaunchKernelGGL((k_welch<T, ACC, 4096, 0, 1>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
   }
 }
 
@@ -850,14 +867,19 @@ gw_status gw_graph_destroy(gw_graph* g) {
 
 gw_status gw_set_tuning(gw_ctx* c, int32_t key, int64_t value) {
   GW_CHECK_CTX(c);
-  if (value < 0 || value > 1) return fail(c, GW_EINVAL, "tuning value must be 0 or 1");
-  if (c->dc.precision == 2 && value != 0) return fail(c, GW_EUNSUPPORTED, "binary64 kernels have one radix order");
   switch (key) {
-    case GW_TUNE_ORD_WINDOW: c->dc.ord_win = int(value); break;
-    case GW_TUNE_ORD_WELCH: c->dc.ord_welch = int(value); break;
+    case GW_TUNE_ORD_WINDOW:
+    case GW_TUNE_ORD_WELCH:
+      if (value < 0 || value > 1) return fail(c, GW_EINVAL, "radix order must be 0 or 1");
+      if (c->dc.precision == 2 && value != 0) return fail(c, GW_EUNSUPPORTED, "binary64 kernels have one radix order");
+      (key == GW_TUNE_ORD_WINDOW ? c->dc.ord_win : c->dc.ord_welch) = int(value);
+      return GW_OK;
+    case GW_TUNE_OCC_WELCH:
+      if (value < 2 || value > 3) return fail(c, GW_EINVAL, "Welch occupancy must be 2 or 3");
+      c->dc.occ_welch = int(value);
+      return GW_OK;
     default: return fail(c, GW_EINVAL, "unknown tuning key");
   }
-  return GW_OK;
 }
 
 gw_status gw_get_tuning(const gw_ctx* c, int32_t key, int64_t* value) {
@@ -865,6 +887,7 @@ gw_status gw_get_tuning(const gw_ctx* c, int32_t key, int64_t* value) {
   switch (key) {
     case GW_TUNE_ORD_WINDOW: *value = c->dc.ord_win; break;
     case GW_TUNE_ORD_WELCH: *value = c->dc.ord_welch; break;
+    case GW_TUNE_OCC_WELCH: *value = c->dc.occ_welch; break;
     default: return GW_EINVAL;
   }
   return GW_OK;
@@ -879,41 +902,49 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(c, GW_EHIP, "hipStreamCreate");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  double ms[2][2] = {{0, 0}, {0, 0}};  // [stage: Welch, window][radix order]
-  const int n_ord = c->dc.precision == 2 ? 1 : 2;
-  const int saved[2] = {c->dc.ord_welch, c->dc.ord_win};
+  // Welch variants: (order, occupancy) = (0,2), (1,2), (0,3), (1,3); window: order 0, 1
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+  const bool b64 = c->dc.precision == 2;
+  const int saved[3] = {c->dc.ord_welch, c->dc.occ_welch, c->dc.ord_win};
+  auto time_stage = [&](int mask, double* res) {
+    s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps && s == GW_OK; ++r)
+      s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess && s == GW_OK) s = fail(c, GW_EHIP, "hipEventSynchronize");
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    *res = double(t) / reps;
+  };
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     s = fail(c, GW_EHIP, "hipEventCreate");
   } else {
     s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, kStageAll, st);
-    for (int stage = 0; stage < 2 && s == GW_OK; ++stage) {
-      for (int o = 0; o < n_ord && s == GW_OK; ++o) {
-        if (stage == 0) c->dc.ord_welch = o; else c->dc.ord_win = o;
-        const int mask = stage == 0 ? kStageWelch : kStageWindow;
-        s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);  // warm-up
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps && s == GW_OK; ++r)
-          s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) { s = fail(c, GW_EHIP, "hipEventSynchronize"); break; }
-        float t = 0.f;
-        (void)hipEventElapsedTime(&t, e0, e1);
-        ms[stage][o] = double(t) / reps;
-      }
+    for (int v = 0; v < 4 && s == GW_OK; ++v) {
+      if (b64 && v > 0) { ms[v] = ms[0]; continue; }
+      c->dc.ord_welch = v & 1;
+      c->dc.occ_welch = 2 + (v >> 1);
+      time_stage(kStageWelch, &ms[v]);
+    }
+    for (int o = 0; o < 2 && s == GW_OK; ++o) {
+      if (b64 && o > 0) { ms[4 + o] = ms[4]; continue; }
+      c->dc.ord_win = o;
+      time_stage(kStageWindow, &ms[4 + o]);
     }
   }
   if (s == GW_OK) {
-    c->dc.ord_welch = (n_ord == 2 && ms[0][1] < ms[0][0]) ? 1 : 0;
-    c->dc.ord_win = (n_ord == 2 && ms[1][1] < ms[1][0]) ? 1 : 0;
-    if (report) {
-      report[0] = ms[0][0];
-      report[1] = n_ord == 2 ? ms[0][1] : ms[0][0];
-      report[2] = ms[1][0];
-      report[3] = n_ord == 2 ? ms[1][1] : ms[1][0];
-    }
+    int best = 0;
+    for (int v = 1; v < 4; ++v)
+      if (ms[v] < ms[best]) best = v;
+    c->dc.ord_welch = b64 ? 0 : (best & 1);
+    c->dc.occ_welch = b64 ? 2 : 2 + (best >> 1);
+    c->dc.ord_win = (!b64 && ms[5] < ms[4]) ? 1 : 0;
+    if (report) std::copy(ms, ms + 6, report);
   } else {
     c->dc.ord_welch = saved[0];
-    c->dc.ord_win = saved[1];
+    c->dc.occ_welch = saved[1];
+    c->dc.ord_win = saved[2];
   }
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);

@@ -39,7 +39,7 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_ragged_offsets", "gw_generate_ragged", "gw_ragged_graph_create",
            "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune")
 
-TUNE_ORD_WINDOW, TUNE_ORD_WELCH = 1, 2
+TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH = 1, 2, 3, 4
 (RQ_B, RQ_OUT_FLOATS, RQ_PSD_FLOATS, RQ_WORKSPACE, RQ_PSD_OFFSET, RQ_NCLASSES) = range(6)
 RAGGED_MAX_CLASSES = 8
@@ -363,11 +363,12 @@ class Generator:
         """Pick the radix orders; returns the mean ms per variant."""
         import torch
         _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
-        rep = (ctypes.c_double * 4)()
+        rep = (ctypes.c_double * 6)()
         nbytes = workspace.numel() * workspace.element_size()
         self._check(lib().gw_autotune(self._h, int(B), _ptr(bg), bg.shape[1], _ptr(out), _ptr(workspace), nbytes,
                                       int(reps), ctypes.cast(rep, ctypes.c_void_p)), "gw_autotune")
-        return {"welch_ord0": rep[0], "welch_ord1": rep[1], "window_ord0": rep[2], "window_ord1": rep[3]}
+        return {"welch_ord0_occ2": rep[0], "welch_ord1_occ2": rep[1], "welch_ord0_occ3": rep[2],
+                "welch_ord1_occ3": rep[3], "window_ord0": rep[4], "window_ord1": rep[5]}
 
 
 class Graph:

@@ -247,16 +247,17 @@ def test_plain_graph_replays_match_eager():
 
 
 @pytest.mark.parametrize("name", ["pr1_plain", "paper_scale"])
-def test_plain_radix_orders_match_oracle(name):
+def test_plain_kernel_variants_match_oracle(name):
     import oracle
     cfg = inputs.config(name)
     bg_np = inputs.background(len(cfg["det_ids"]), 1 << 20, cfg["fs"], seed=1)
     bg = _gpu(bg_np)
     B = 6
-    for ow, ol in ((1, 1), (0, 1), (1, 0)):
+    for ow, ol, occ in ((1, 1, 2), (0, 1, 3), (1, 0, 3)):
         gen = gwgen.Generator(cfg)
         gen.set_tuning(gwgen.TUNE_ORD_WINDOW, ow)
         gen.set_tuning(gwgen.TUNE_ORD_WELCH, ol)
+        gen.set_tuning(gwgen.TUNE_OCC_WELCH, occ)
         out = torch.empty((B, len(cfg["det_ids"]), gen.sizes["N"]), dtype=torch.float32, device=DEV)
         ws = gen.alloc_workspace(B)
         gen.generate_batch(5, 0, B, bg, out, ws)
@@ -267,7 +268,7 @@ def test_plain_radix_orders_match_oracle(name):
         g = out.cpu().numpy()
         for i in range(B):
             for d in range(len(cfg["det_ids"])):
-                assert rel_l2(g[i, d], ref[i, d]) <= TOL_STRAIN, (name, ow, ol, i, d)
+                assert rel_l2(g[i, d], ref[i, d]) <= TOL_STRAIN, (name, ow, ol, occ, i, d)
 
 
 def test_autotuners_keep_results():
