@@ -14,7 +14,6 @@ Prints one JSON line.
 """
 
 import argparse
-import hashlib
 import json
 import math
 import multiprocessing as mp
@@ -31,34 +30,11 @@ HBM_PEAK_GBS = 8000.0
 # build): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_PEAK_PACKED_TFLOPS = 157.3
-WELCH_SRC = os.path.join(ROOT, "paper_2407_19048_amd", "csrc")
 
 
 def log(msg):
     sys.stderr.write(msg + "\n")
     sys.stderr.flush()
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(WELCH_SRC)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(WELCH_SRC, f), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        d = json.load(fh)
-    if d.get("source_hash") != kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
 
 
 # ------------------------------------------------------------ CPU baseline
@@ -213,7 +189,8 @@ def ragged_leg(bg2048, args, K, W, dev):
     table = rg.autotune(bgs, out, ws, reps=3)
     tuned = {"ord_window": rg.get_tuning(gwgen.RTUNE_ORD_WINDOW), "ord_welch": rg.get_tuning(gwgen.RTUNE_ORD_WELCH),
              "grid_window": rg.get_tuning(gwgen.RTUNE_GRID_WINDOW),
-             "grid_welch": rg.get_tuning(gwgen.RTUNE_GRID_WELCH)}
+             "grid_welch": rg.get_tuning(gwgen.RTUNE_GRID_WELCH),
+             "window_mode": rg.get_tuning(gwgen.RTUNE_WINDOW_MODE)}
     log("ragged autotune %s -> %s" % (table, tuned))
     graph = rg.graph(2, 0, bgs, out, ws, params_f32=pf, status=st)
     for _ in range(W):
@@ -251,7 +228,7 @@ def ragged_leg(bg2048, args, K, W, dev):
         "bytes_per_step": nbytes, "class_counts": np.bincount(cls, minlength=len(classes)).tolist(),
         "stage_ms": {"welch": round(welch_best, 4), "window": round(win_best, 4)},
         "autotune_ms": {"welch_ord%d_grid%d" % k: round(v, 4) for k, v in table["welch"].items()}
-        | {"window_ord%d" % k: round(v, 4) for k, v in table["window"].items()},
+        | {"window_mode%d_ord%d" % k: round(v, 4) for k, v in table["window"].items()},
         "tuned": tuned,
     }
 
@@ -362,6 +339,7 @@ def main():
     L = z["L"]
     welch_flops = B * n_det * z["K"] * (2.5 * L * math.log2(L) + 3.0 * L)
     welch_tflops = welch_flops / (welch_ms * 1e-3) / 1e12
+    from paper_2407_19048_amd.profiling import measured_traffic
     traffic = measured_traffic("k_welch", "paper_scale_B%d" % B)
 
     if args.copy_probe_gib > 0:

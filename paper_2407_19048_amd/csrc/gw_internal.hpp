@@ -13,6 +13,7 @@ struct gw_ctx {
   gw::DevCfg dc;
   double* kcbrt = nullptr;    // [F]  k^(1/3)
   double* lnk3 = nullptr;     // [F]  ln(k)/3
+  double* k53 = nullptr;      // [F]  k^(-5/3) (0 at k = 0)
   void* tw_win = nullptr;     // cpx<T>[N/2]
   void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
   void* tw_welch = nullptr;   // cpx<T>[L]

@@ -87,6 +87,7 @@ struct WinArgs {
   uint32_t* status;
   const double* kcbrt;
   const double* lnk3;
+  const double* k53;      // k^(-5/3) (SRC 3)
   const void* tw;         // cpx<T>[N/2], exp(-2 pi i n / (N/2))
   const void* twr;        // cpx<T>[N/4 + 1], exp(-2 pi i k / N)
   const WfScalars* wf;    // [B] (SRC 1, 3)
@@ -135,22 +136,22 @@ template <class T>
 __device__ __forceinline__ cpx<T> signal_bin_surr(const DevCfg& cf, const WinArgs& a, const WfScalars& w,
                                                   const float* nd, T cpl, T cxx, double tauT, int k) {
   if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
-  const double kc = a.kcbrt[k], lk3 = a.lnk3[k];
+  const double lk3 = a.lnk3[k], k53 = a.k53[k];
   // u = (ln(Ms k / T) - ln Mf_lo) / dlog, ln(Ms/T) = 3 ln v1 - ln pi
-  const float u = float((3.0 * w.lnv1 - 1.1447298858494002 + 3.0 * lk3 - kSurrLnMfLo) * (1.0 / kSurrDlog));
+  const float u = float((3.0 * w.lnv1 - 1.1447298858494002 - kSurrLnMfLo + 3.0 * lk3) * (1.0 / kSurrDlog));
   const float uc = fminf(fmaxf(u, 0.f), float(kSurrNodes - 1));
   const int i = min(int(uc), kSurrNodes - 2);
   const float tt = uc - float(i);
   const float ratio = (1.f - tt) * nd[i] + tt * nd[i + 1];
   const float dpsi = (1.f - tt) * nd[kSurrNodes + i] + tt * nd[kSurrNodes + i + 1];
-  const double v = w.v1 * kc;
-  const double iv = rcp_t(v);
-  const double iv2 = iv * iv;
-  double rev = w.a[0] * iv2 * iv2 * iv + double(dpsi) * (1.0 / (2.0 * kPi)) + w.pconst + double(k) * tauT;
+  // Newtonian phase cN k^(-5/3) from the table: one binary64 product per bin
+  double rev = w.cN * k53 + double(dpsi) * (1.0 / (2.0 * kPi)) + w.pconst + double(k) * tauT;
   rev = frac1(rev);
   T sn, cs;
   sincos_rev(T(rev), &sn, &cs);
-  const T A = T(cf.fs) * T(w.A0T) * rsqrt_t(T(kc)) * rcp_t(T(k)) * T(ratio);
+  // A_N(f_k) = A0T k^(-7/6) = A0T k^(-5/3) k^(1/2)
+  const T kf = T(k);
+  const T A = T(cf.fs) * T(w.A0T) * T(k53) * (kf * rsqrt_t(kf)) * T(ratio);
   return {A * (cpl * cs - cxx * sn), -A * (cpl * sn + cxx * cs)};
 }
 

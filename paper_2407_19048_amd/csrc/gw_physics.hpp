@@ -106,6 +106,7 @@ struct WfScalars {
   double f_rd, inv_fdamp;
   double At, Ard, ft, fdamp2;
   double Apl;           // At (f_t T)^(2/3): power-law amplitude Apl k^(-2/3) between f_t and f_RD
+  double cN;            // Newtonian phase in revolutions at bin k: cN k^(-5/3)
   int kend, kt, krd;    // band end; first bins with f >= f_t and f >= f_RD
   int cut_nyquist;
   double cosi, tc, ra, dec, psi;
@@ -184,6 +185,7 @@ __device__ __forceinline__ void wf_setup(const double* __restrict__ params, int6
   w.b6 = rev * lg[6];
   w.v1 = cbrt(kPi * Ms * cf.invT);
   w.lnv1 = log(w.v1);
+  w.cN = w.a[0] / (w.v1 * w.v1 * w.v1 * w.v1 * w.v1);
   w.pconst = (-phic - 0.25 * kPi) / (2.0 * kPi);
   const double A0 = kStrainScale * sqrt(5.0 / 24.0) * pow(kPi, -2.0 / 3.0) *
                     pow(mc * kMsunSec, 5.0 / 6.0) / (dl * kMpcSec);

@@ -62,6 +62,8 @@ struct gw_ragged {
   void* twr[4] = {nullptr, nullptr, nullptr, nullptr};  // exp(-2 pi i k / 2M), k <= M/2
   int n_cu = 256;
   int ord_win = 0, ord_welch = 0, grid_win = 1, grid_welch = 2;
+  int win_mode = 0;                      // 0: one persistent launch, 1: one launch per class
+  int cls_first[kMaxCls], cls_items[kMaxCls];  // window item range of each class
   std::string err;
 };
 
@@ -238,6 +240,33 @@ __global__ __launch_bounds__(kWinThreads) void k_window_ragged(RWinArgs a) {
   window_size_loop<TP, 2048, ORD>(a, g, a.end[0], t, lds, &s_g, sflag);
 }
 
+// Window stage issued per class: one NC/16-thread workgroup per item of
+// class `cls` (items first .. first + gridDim.x - 1), at the occupancy of the
+// batch kernel of that size.
+template <int NC> struct ClassOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
+
+template <class TP, int NC, int ORD>
+__global__ __launch_bounds__(NC / 16, ClassOcc<NC>::value) void k_window_class(RWinArgs a, int cls, int first) {
+  constexpr int LS = LdsSize<NC>::value, S = Log2Sub2048<NC>::value;
+  __shared__ float lds[2 * LS];
+  __shared__ uint32_t sflag;
+  const int t = threadIdx.x;
+  if (t == 0) sflag = 0u;
+  const int it = load_const(a.items + first + int(blockIdx.x));
+  const DevCfg cf = load_const(a.cfgs + cls);
+  const int D = cf.n_det;
+  const int b = it / D, d = it - b * D;
+  const float* x = a.bg[cls] + int64_t(d) * a.L_bg[cls] + load_const(a.w.offset + b) + cf.P;
+  const float* psd = a.psd + load_const(a.psd_off + b) + int64_t(d) * cf.Fw;
+  float* o = a.w.out + load_const(a.out_off + b) + int64_t(d) * cf.N;
+  window_item<float, TP, false, NC, 1, ORD>(cf, a.w, t, b, d, x, nullptr, nullptr, psd, o,
+                                            reinterpret_cast<const cpx<float>*>(a.tw[S]),
+                                            reinterpret_cast<const cpx<float>*>(a.twr[S]), lds, lds + LS, true,
+                                            &sflag);
+  __syncthreads();
+  if (t == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
+}
+
 __global__ void k_fill_u32_r(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i < n) p[i] = v;
@@ -329,8 +358,33 @@ void launch_welch_ragged(const gw_ragged* r, const RWelchArgs& a, hipStream_t st
   else hipLaunchKernelGGL((k_welch_ragged<ACC, 0>), grid, dim3(kWelchThreads), 0, st, a);
 }
 
+template <class TP, int ORD>
+void launch_window_class(const gw_ragged* r, const RWinArgs& a, int c, hipStream_t st) {
+  const dim3 grid = dim3(unsigned(r->cls_items[c]));
+  const int first = r->cls_first[c];
+  switch (r->dc[c].N / 2) {
+    case 16384: hipLaunchKernelGGL((k_window_class<TP, 16384, ORD>), grid, dim3(1024), 0, st, a, c, first); break;
+    case 8192: hipLaunchKernelGGL((k_window_class<TP, 8192, ORD>), grid, dim3(512), 0, st, a, c, first); break;
+    case 4096: hipLaunchKernelGGL((k_window_class<TP, 4096, 0>), grid, dim3(256), 0, st, a, c, first); break;
+    default: hipLaunchKernelGGL((k_window_class<TP, 2048, ORD>), grid, dim3(128), 0, st, a, c, first); break;
+  }
+}
+
 template <class TP>
 void launch_window_ragged(const gw_ragged* r, const RWinArgs& a, hipStream_t st) {
+  if (r->win_mode == 1) {
+    // largest transforms first, as in the persistent queue
+    int order[kMaxCls];
+    for (int c = 0; c < r->n_cls; ++c) order[c] = c;
+    std::stable_sort(order, order + r->n_cls, [&](int x, int y) { return r->dc[x].N > r->dc[y].N; });
+    for (int k = 0; k < r->n_cls; ++k) {
+      const int c = order[k];
+      if (r->cls_items[c] == 0) continue;
+      if (r->ord_win) launch_window_class<TP, 1>(r, a, c, st);
+      else launch_window_class<TP, 0>(r, a, c, st);
+    }
+    return;
+  }
   const dim3 grid = dim3(unsigned(r->n_cu * r->grid_win));
   if (r->ord_win) hipLaunchKernelGGL((k_window_ragged<TP, 1>), grid, dim3(kWinThreads), 0, st, a);
   else hipLaunchKernelGGL((k_window_ragged<TP, 0>), grid, dim3(kWinThreads), 0, st, a);
@@ -513,6 +567,11 @@ gw_status gw_ragged_create(const gw_config* classes, int32_t n_classes, const in
   std::vector<int32_t> wi, vi;
   build(true, wg, wi);
   build(false, vg, vi);
+  for (int c = 0; c < kMaxCls; ++c) r->cls_first[c] = r->cls_items[c] = 0;
+  for (const int4& g : vg) {
+    if (r->cls_items[g.x] == 0) r->cls_first[g.x] = g.y;
+    r->cls_items[g.x] += g.z;
+  }
   r->n_wgroups = int(wg.size());
   r->n_vgroups = int(vg.size());
   // sizes appear in decreasing order: the groups of size slot s end where
@@ -631,6 +690,10 @@ gw_status gw_ragged_set_tuning(gw_ragged* r, int32_t key, int64_t value) {
       if (value < 1 || value > 8) return rfail(r, GW_EINVAL, "grid must be 1..8 workgroups per CU");
       (key == GW_RTUNE_GRID_WINDOW ? r->grid_win : r->grid_welch) = int(value);
       return GW_OK;
+    case GW_RTUNE_WINDOW_MODE:
+      if (value < 0 || value > 1) return rfail(r, GW_EINVAL, "window mode must be 0 or 1");
+      r->win_mode = int(value);
+      return GW_OK;
     default: return rfail(r, GW_EINVAL, "unknown tuning key");
   }
 }
@@ -642,6 +705,7 @@ gw_status gw_ragged_get_tuning(const gw_ragged* r, int32_t key, int64_t* value) 
     case GW_RTUNE_ORD_WELCH: *value = r->ord_welch; break;
     case GW_RTUNE_GRID_WINDOW: *value = r->grid_win; break;
     case GW_RTUNE_GRID_WELCH: *value = r->grid_welch; break;
+    case GW_RTUNE_WINDOW_MODE: *value = r->win_mode; break;
     default: return GW_EINVAL;
   }
   return GW_OK;
@@ -657,9 +721,9 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return rfail(r, GW_EHIP, "hipStreamCreate");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const int saved[4] = {r->ord_welch, r->grid_welch, r->ord_win, r->grid_win};
+  const int saved[5] = {r->ord_welch, r->grid_welch, r->ord_win, r->grid_win, r->win_mode};
   const int grids[3] = {1, 2, 4};
-  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   auto time_stage = [&](int stage, double* res) {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, stage, st);  // warm-up
     (void)hipEventRecord(e0, st);
@@ -681,11 +745,13 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
         r->grid_welch = grids[gi];
         time_stage(kStageWelch, &ms[o * 3 + gi]);
       }
-    for (int o = 0; o < 2 && s == GW_OK; ++o) {
-      r->ord_win = o;
-      r->grid_win = saved[3];
-      time_stage(kStageWindow, &ms[6 + o]);
-    }
+    for (int m = 0; m < 2 && s == GW_OK; ++m)
+      for (int o = 0; o < 2 && s == GW_OK; ++o) {
+        r->ord_win = o;
+        r->win_mode = m;
+        r->grid_win = saved[3];
+        time_stage(kStageWindow, &ms[6 + 2 * m + o]);
+      }
   }
   if (s == GW_OK) {
     int best = 0;
@@ -693,13 +759,18 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
       if (ms[k] < ms[best]) best = k;
     r->ord_welch = best / 3;
     r->grid_welch = grids[best % 3];
-    r->ord_win = ms[7] < ms[6] ? 1 : 0;
-    if (report) std::copy(ms, ms + 8, report);
+    int bw = 6;
+    for (int k = 7; k < 10; ++k)
+      if (ms[k] < ms[bw]) bw = k;
+    r->win_mode = (bw - 6) / 2;
+    r->ord_win = (bw - 6) % 2;
+    if (report) std::copy(ms, ms + 10, report);
   } else {
     r->ord_welch = saved[0];
     r->grid_welch = saved[1];
     r->ord_win = saved[2];
     r->grid_win = saved[3];
+    r->win_mode = saved[4];
   }
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);

@@ -447,6 +447,7 @@ static WinArgs win_args(gw_ctx* c) {
   a.cf = c->dc;
   a.kcbrt = c->kcbrt;
   a.lnk3 = c->lnk3;
+  a.k53 = c->k53;
   a.tw = c->tw_win;
   a.twr = c->twr_win;
   return a;
@@ -570,6 +571,7 @@ gw_status gw_destroy(gw_ctx* c) {
   if (!c) return GW_OK;
   (void)hipFree(c->kcbrt);
   (void)hipFree(c->lnk3);
+  (void)hipFree(c->k53);
   (void)hipFree(c->tw_win);
   (void)hipFree(c->twr_win);
   (void)hipFree(c->tw_welch);
@@ -587,18 +589,21 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
   gw_ctx* c = new gw_ctx();
   c->cfg = *cfg;
   c->dc = dc;
-  std::vector<double> hc(dc.F), hl(dc.F);
+  std::vector<double> hc(dc.F), hl(dc.F), h53(dc.F);
   for (int k = 0; k < dc.F; ++k) {
     hc[k] = std::cbrt(double(k));
     hl[k] = k > 0 ? std::log(double(k)) / 3.0 : 0.0;
+    h53[k] = k > 0 ? std::pow(double(k), -5.0 / 3.0) : 0.0;
   }
   if (hipMalloc(&c->kcbrt, sizeof(double) * dc.F) != hipSuccess ||
-      hipMalloc(&c->lnk3, sizeof(double) * dc.F) != hipSuccess) {
+      hipMalloc(&c->lnk3, sizeof(double) * dc.F) != hipSuccess ||
+      hipMalloc(&c->k53, sizeof(double) * dc.F) != hipSuccess) {
     gw_destroy(c);
     return GW_ENOMEM;
   }
   if (hipMemcpy(c->kcbrt, hc.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->lnk3, hl.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->lnk3, hl.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->k53, h53.data(), sizeof(double) * dc.F, hipMemcpyHostToDevice) != hipSuccess) {
     gw_destroy(c);
     return GW_EHIP;
   }

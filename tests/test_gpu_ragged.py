@@ -110,12 +110,13 @@ def _balanced(B, n=6, seed=5):
     return cls
 
 
-def test_ragged_all_classes_match_oracle():
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_all_classes_match_oracle(mode):
     classes = inputs.ragged_classes()
     cls = _balanced(18)
     bgs = class_bgs(classes, 19)
-    _say("ragged parity: B=18, six classes")
-    r = run_ragged(classes, cls, 7, 2, bgs)
+    _say("ragged parity: B=18, six classes, window mode %d" % mode)
+    r = run_ragged(classes, cls, 7, 2, bgs, tune={gwgen.RTUNE_WINDOW_MODE: mode})
     worst = check_slots(classes, cls, 7, 2, bgs, r, list(range(18)))
     _say("ragged worst rel L2 %.3e" % worst)
     np.testing.assert_array_equal(r["pf"], r["params"].astype(np.float32))
@@ -205,11 +206,13 @@ def _rel_graph_check(make_eager, graph, out_g, n=3, first=5):
     assert np.array_equal(out_g.cpu().numpy(), make_eager(first))
 
 
-def test_ragged_graph_replays_match_eager():
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_graph_replays_match_eager(mode):
     classes = inputs.ragged_classes()
     bgs_np = class_bgs(classes, 19)
     cls = _balanced(12, seed=4)
     rg = gwgen.Ragged(classes, cls)
+    rg.set_tuning(gwgen.RTUNE_WINDOW_MODE, mode)
     bgs = [_gpu(b) for b in bgs_np]
     out_g, ws_g = rg.alloc_out(), rg.alloc_workspace()
     st_g = torch.zeros(rg.B, dtype=torch.int32, device=DEV)
@@ -302,7 +305,8 @@ def test_autotuners_keep_results():
     _say("ragged autotune: %s" % table)
     assert all(v > 0 for v in table["welch"].values()) and all(v > 0 for v in table["window"].values())
     tuned = {k: rg.get_tuning(k) for k in (gwgen.RTUNE_ORD_WINDOW, gwgen.RTUNE_ORD_WELCH,
-                                          gwgen.RTUNE_GRID_WINDOW, gwgen.RTUNE_GRID_WELCH)}
+                                          gwgen.RTUNE_GRID_WINDOW, gwgen.RTUNE_GRID_WELCH,
+                                          gwgen.RTUNE_WINDOW_MODE)}
     _say("ragged tuned: %s" % tuned)
     r = run_ragged(classes, cls, 4, 0, bgs_np, tune=tuned)
     check_slots(classes, cls, 4, 0, bgs_np, r, list(range(0, 24, 3)))
