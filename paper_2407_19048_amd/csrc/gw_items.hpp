@@ -167,10 +167,18 @@ template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
 __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, int t, int64_t b, int d,
                                             const float* x, const float* hrow, const float* nz, const float* psd,
                                             float* o, const cpx<T>* twtab, const cpx<T>* twr, T* sre, T* sim,
-                                            bool active, uint32_t* sflag) {
+                                            bool active, uint32_t* sflag, float* snodes = nullptr) {
   constexpr int NT = NC / 16;
   static_assert(SRC >= 0 && SRC <= 3, "source");
   PowTwiddle<T, NC, ORD> tw{twtab};
+  if constexpr (SRC == 3) {
+    // the sample's node values go to LDS once; the barriers of the forward
+    // transform below make them visible to the whole (sub-)block
+    if (snodes) {
+      const float* src = a.nodes + b * 2 * kSurrNodes;
+      for (int i = t; i < 2 * kSurrNodes; i += NT) snodes[i] = src[i];
+    }
+  }
   cpx<T> v[16];
   uint32_t flag = 0;
   if constexpr (SRC != 2) {
@@ -200,6 +208,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   if constexpr (SRC == 3) {
     use_surr = !(load_const(a.logmm + b) > a.logmm_max);
     nd = a.nodes + b * 2 * kSurrNodes;
+    if (snodes) nd = snodes;  // staged before the forward transform
     if (active && !use_surr && t == 0 && d == 0 && a.status)
       atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
   }

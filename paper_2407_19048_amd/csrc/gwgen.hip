@@ -137,6 +137,7 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
   constexpr int LS = LdsSize<NC>::value;
   __shared__ T lds[2 * LS];
   __shared__ uint32_t sflag;
+  __shared__ float snodes[SRC == 3 ? 2 * kSurrNodes : 1];
   const int t = threadIdx.x;
   const int64_t bd = blockIdx.x;
   const int D = a.cf.n_det;
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
   } else x = a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
   window_item<T, TP, FULL, NC, SRC, ORD>(a.cf, a, t, b, d, x, hrow, nz, a.psd + bd * a.cf.Fw, a.out + bd * N,
                                          reinterpret_cast<const cpx<T>*>(a.tw), reinterpret_cast<const cpx<T>*>(a.twr),
-                                         lds, lds + LS, true, &sflag);
+                                         lds, lds + LS, true, &sflag, SRC == 3 ? snodes : nullptr);
   __syncthreads();
   if (t == 0 && sflag && a.status) atomicOr(a.status + b, sflag);
 }
