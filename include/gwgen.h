@@ -201,6 +201,38 @@ gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Per-run PSD mode (section 3.2 fits one noise spectrum to the background
+ * chunk held on the accelerator): one Welch PSD per detector for the run,
+ * turned into a truncated whitening filter, then batches that only
+ * generate, inject and whiten.
+ * ------------------------------------------------------------------------ */
+/* Bytes of workspace gw_run_psd needs. */
+gw_status gw_run_psd_workspace_size(const gw_ctx* ctx, int64_t n_chunks, int64_t* bytes);
+/* Welch PSD of each detector row over its first n_chunks*K segments
+ * (segment s starts at s*S), computed as the mean of n_chunks psd_length
+ * stretches starting at c*K*S.  bg: float [n_det][L_bg] (4-byte aligned);
+ * psd: float [n_det][L/2+1].  Requires (n_chunks-1)*K*S + P <= L_bg. */
+gw_status gw_run_psd(gw_ctx* ctx, const float* bg, int64_t L_bg, int64_t n_chunks, float* psd,
+                     void* workspace, int64_t workspace_bytes, hipStream_t stream);
+/* Truncated whitening filter per detector: the gain 1/sqrt(fs S/2) on the
+ * window grid (S linearly interpolated from psd [n_det][L/2+1]; zero below
+ * f_min, at DC and at Nyquist), its impulse response (inverse real
+ * transform of length N) multiplied by cos^2(pi n / M) for circular lags
+ * |n| < M/2 and by 0 elsewhere, then the magnitude of the forward transform.
+ * filt: float [n_det][N/2+1].  M even, 2 <= M < N (M = fduration * fs). */
+gw_status gw_whiten_filter(gw_ctx* ctx, const float* psd, int64_t M, float* filt, hipStream_t stream);
+/* gw_generate_batch with the fixed filters in place of per-sample Welch
+ * PSDs: same prior draws and windows (same seed gives the same parameters
+ * and offsets), whitening Y_k = X_k filt[d][k], and the first and last
+ * `crop` samples of each window dropped (crop even, 2 crop < N; normally
+ * M/2).  out: float [B][n_det][N - 2 crop].  Workspace as for
+ * gw_generate_batch (its PSD region is unused). */
+gw_status gw_generate_batch_runpsd(gw_ctx* ctx, uint64_t seed, uint64_t batch_index, int64_t B,
+                                   const float* bg, int64_t L_bg, const float* filt, int64_t crop,
+                                   float* out, float* params_f32, uint32_t* status,
+                                   void* workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Captured batch pipelines (HIP graphs).  A gw_graph replays the kernels of
  * one batch with the pointers given at creation; every launch then advances
  * a batch counter kept in the workspace, so replay r (counting from 0 after

@@ -25,7 +25,7 @@ import numpy as np
 
 from .detectors import antenna_patterns, detector_geometry, time_delays
 from .priors import sample_params
-from .spectral import interp_psd, welch_psd, whiten
+from .spectral import interp_psd, run_psd, truncated_filter, welch_psd, whiten, whiten_filtered
 from .waveform import fd_waveform
 
 
@@ -140,3 +140,27 @@ def generate_ragged(classes, cls, seed, batch_index, bgs, slots=None):
         c = int(cls[i])
         outs[i] = generate_sample(classes[c], bgs[c], params[:, i], int(offsets[i]))
     return outs, params, offsets
+
+
+def run_psds(cfg, bg, n_chunks):
+    """Per-run PSD of every detector row [D][L/2+1]: Welch over the first
+    n_chunks * K segments of the row (K segments per psd_length stretch)."""
+    z = derived_sizes(cfg)
+    return np.stack([run_psd(bg[d], float(cfg["fs"]), z["L"], z["S"], n_chunks * z["K"])
+                     for d in range(bg.shape[0])])
+
+
+def run_filters(cfg, psd, M):
+    """Truncated whitening filters [D][N/2+1] from per-run PSDs [D][L/2+1]."""
+    z = derived_sizes(cfg)
+    return np.stack([truncated_filter(interp_psd(psd[d], z["r"]), float(cfg["fs"]), z["N"],
+                                      float(cfg["f_min"]), M) for d in range(psd.shape[0])])
+
+
+def generate_sample_runpsd(cfg, bg, p, offset, filt, crop):
+    """Per-run mode: the sample's window (as in generate_sample) whitened with
+    the detector's fixed filter, `crop` samples dropped at each end."""
+    hp, hc = waveform_on_grid(cfg, p)
+    H = project_detectors(cfg, p, hp, hc)
+    y = inject(cfg, bg, offset, H)
+    return np.stack([whiten_filtered(y[d], filt[d], crop) for d in range(y.shape[0])])

@@ -18,6 +18,18 @@ paper gives no estimator details; the readings used here:
     0 < k < N/2, zero elsewhere (also zero where S_w[k] is not a positive
     finite number); output irfft(Y).  No taper, no truncation.
 
+Per-run mode (one PSD per detector for the whole run, then whitening with
+a truncated inverse-spectrum filter):
+  * run PSD: Welch as above over the first n_seg segments of the background
+    row (the paper fits one spectrum to its background chunk);
+  * the whitening gain g[k] above is turned into a finite impulse response
+    of M taps: q = irfft_N(g), q_t[n] = q[n] cos^2(pi n / M) for |n| < M/2
+    (n taken circularly in (-N/2, N/2]), 0 elsewhere; the filter is
+    |rfft_N(q_t)| (the truncation smooths the gain; taking the magnitude
+    drops the sign of the small negative ripples next to sharp cuts);
+  * whitened output: irfft(rfft(y) * filter) with M/2 samples dropped at
+    each end, where the filter's circular wrap-around reaches.
+
 Pins: Welch equals scipy.signal.welch with the same settings; white noise
 gives a flat PSD at 2 sigma^2/fs; noise with a known PSD whitened by that PSD
 has variance 2 n_kept / N; a noise-free signal whitened by the true PSD has
@@ -74,3 +86,46 @@ def whiten(y, psd_w, fs, f_low):
     out = np.zeros_like(Y)
     out[keep] = Y[keep] / np.sqrt(fs * psd_w[keep] / 2.0)
     return np.fft.irfft(out, n=N)
+
+
+def whitening_gain(psd_w, fs, N, f_low):
+    """g[k] = 1 / sqrt(fs S_w[k] / 2) on the kept bins, 0 elsewhere ([N/2+1])."""
+    psd_w = np.asarray(psd_w, dtype=np.float64)
+    f = np.arange(N // 2 + 1) * fs / N
+    keep = (f >= f_low) & np.isfinite(psd_w) & (psd_w > 0.0)
+    keep[0] = False
+    keep[N // 2] = False
+    g = np.zeros(N // 2 + 1)
+    g[keep] = 1.0 / np.sqrt(fs * psd_w[keep] / 2.0)
+    return g
+
+
+def truncation_taper(N, M):
+    """cos^2(pi n / M) for circular lags |n| < M/2, else 0 ([N])."""
+    n = np.arange(N)
+    n = np.where(n > N // 2, n - N, n)
+    return np.where(np.abs(n) < M / 2.0, np.cos(np.pi * n / M) ** 2, 0.0)
+
+
+def truncated_gain(psd_w, fs, N, f_low, M):
+    """rfft_N of the tapered impulse response of the whitening gain (real)."""
+    q = np.fft.irfft(whitening_gain(psd_w, fs, N, f_low), n=N)
+    return np.real(np.fft.rfft(q * truncation_taper(N, M)))
+
+
+def truncated_filter(psd_w, fs, N, f_low, M):
+    """Whitening filter of the per-run mode: |truncated_gain| ([N/2+1])."""
+    return np.abs(truncated_gain(psd_w, fs, N, f_low, M))
+
+
+def whiten_filtered(y, filt, crop):
+    """irfft(rfft(y) * filt) with `crop` samples dropped at each end."""
+    y = np.asarray(y, dtype=np.float64)
+    N = y.shape[0]
+    out = np.fft.irfft(np.fft.rfft(y) * np.asarray(filt, dtype=np.float64), n=N)
+    return out[crop:N - crop]
+
+
+def run_psd(x, fs, L, S, n_seg):
+    """Welch PSD over the first n_seg segments of the 1-D row x."""
+    return welch_psd(np.asarray(x)[:(n_seg - 1) * S + L], fs, L, S)

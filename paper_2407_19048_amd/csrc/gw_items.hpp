@@ -95,6 +95,7 @@ struct WinArgs {
   const float* nodes;     // [B][2][1024] surrogate node values (SRC 3)
   const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
   float logmm_max;        // fallback threshold (SRC 3)
+  int crop;               // samples dropped at each end of the output (SRC 4; even)
 };
 
 // Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
@@ -112,6 +113,14 @@ __device__ __forceinline__ T whiten_gain(const DevCfg& cf, const float* psd, int
   if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
   if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
   return rsqrt_t(T(cf.fs) * S * T(0.5));
+}
+
+// Gain of a precomputed whitening filter at bin k; sets status bits.
+template <class T>
+__device__ __forceinline__ T filter_gain(const float* filt, int k, uint32_t& flag) {
+  const float g = filt[k];
+  if (!isfinite(g)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
+  return T(g);
 }
 
 // Projected signal (DFT coefficients) at window bin k, generated in registers.
@@ -161,6 +170,8 @@ __device__ __forceinline__ cpx<T> signal_bin_surr(const DevCfg& cf, const WinArg
 // signal + whiten (x = background at o + P).  SRC 3: as SRC 1 with the signal
 // from surrogate node values (plain model where the predicted mismatch
 // exceeds the threshold).  SRC 2: inject (hrow = hdet row, nz = noise window).
+// SRC 4: as SRC 1 whitened with a fixed per-run filter (psd = filter row of
+// N/2 + 1 gains), storing samples [crop, N - crop) only.
 // `active` false: compute on the given (valid) item but store nothing, so
 // that idle sub-blocks still meet every block barrier.
 template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
@@ -169,7 +180,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
                                             float* o, const cpx<T>* twtab, const cpx<T>* twr, T* sre, T* sim,
                                             bool active, uint32_t* sflag, float* snodes = nullptr) {
   constexpr int NT = NC / 16;
-  static_assert(SRC >= 0 && SRC <= 3, "source");
+  static_assert(SRC >= 0 && SRC <= 4, "source");
   PowTwiddle<T, NC, ORD> tw{twtab};
   if constexpr (SRC == 3) {
     // the sample's node values go to LDS once; the barriers of the forward
@@ -202,7 +213,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   T cpl = T(0), cxx = T(0);
   double tauT = 0.0;
   WfScalars wsh;
-  if constexpr (SRC == 1 || SRC == 3) wsh = load_const(a.wf + b);
+  if constexpr (SRC == 1 || SRC == 3 || SRC == 4) wsh = load_const(a.wf + b);
   bool use_surr = false;
   const float* nd = nullptr;
   if constexpr (SRC == 3) {
@@ -212,7 +223,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     if (active && !use_surr && t == 0 && d == 0 && a.status)
       atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
   }
-  if constexpr (SRC == 1 || SRC == 3) {
+  if constexpr (SRC == 1 || SRC == 3 || SRC == 4) {
     const DetScalars dsh = load_const(a.dsc + (b * cf.n_det + d));
     cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
     cxx = T(dsh.fx * wsh.cosi);
@@ -241,7 +252,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
       cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
       cpx<T> Xm = {T(0.5) * (s.x - u.y), T(0.5) * (-s.y - u.x)};
-      if constexpr (SRC == 1) {
+      if constexpr (SRC == 1 || SRC == 4) {
         Xk = cadd(Xk, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, k));
         if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, km));
       } else if constexpr (SRC == 3) {
@@ -253,8 +264,14 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
           if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, km));
         }
       }
-      Yk = cscale(Xk, whiten_gain<T>(cf, psd, k, NC, flag));
-      Ym = cscale(Xm, whiten_gain<T>(cf, psd, km, NC, flag));
+      if constexpr (SRC == 4) {
+        // fixed per-run filter row [NC + 1] (zero outside the kept band)
+        Yk = cscale(Xk, filter_gain<T>(psd, k, flag));
+        Ym = cscale(Xm, filter_gain<T>(psd, km, flag));
+      } else {
+        Yk = cscale(Xk, whiten_gain<T>(cf, psd, k, NC, flag));
+        Ym = cscale(Xm, whiten_gain<T>(cf, psd, km, NC, flag));
+      }
       if (km == k) Ym = Yk;
     }
     // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
@@ -281,7 +298,13 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
         y.x += nz[2 * n];
         y.y += nz[2 * n + 1];
       }
-      reinterpret_cast<float2*>(o)[n] = y;
+      if constexpr (SRC == 4) {
+        // cropped store: samples [crop, N - crop), crop even
+        const int m = n - (a.crop >> 1);
+        if (m >= 0 && m < NC - a.crop) reinterpret_cast<float2*>(o)[m] = y;
+      } else {
+        reinterpret_cast<float2*>(o)[n] = y;
+      }
     }
     if (flag) atomicOr(sflag, flag);
   }

@@ -153,7 +153,9 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
     hrow = a.src + bd * 2 * (NC + 1);
     nz = a.bg + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
   } else x = a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
-  window_item<T, TP, FULL, NC, SRC, ORD>(a.cf, a, t, b, d, x, hrow, nz, a.psd + bd * a.cf.Fw, a.out + bd * N,
+  const float* psd = SRC == 4 ? a.psd + int64_t(d) * (NC + 1) : a.psd + bd * a.cf.Fw;
+  float* o = a.out + bd * (SRC == 4 ? N - 2 * a.crop : N);
+  window_item<T, TP, FULL, NC, SRC, ORD>(a.cf, a, t, b, d, x, hrow, nz, psd, o,
                                          reinterpret_cast<const cpx<T>*>(a.tw), reinterpret_cast<const cpx<T>*>(a.twr),
                                          lds, lds + LS, true, &sflag, SRC == 3 ? snodes : nullptr);
   __syncthreads();
@@ -197,6 +199,125 @@ __global__ void k_set_u64(uint64_t* p, uint64_t v) {
 
 __global__ void k_add_u64(uint64_t* p, uint64_t v) {
   if (threadIdx.x == 0) *p += v;
+}
+
+// ------------------------------------------------------- per-run PSD mode
+// Chunk c of the run PSD covers segments [cK, (c+1)K): its stretch starts at c K S.
+__global__ void k_chunk_offsets(int64_t* off, int64_t n, int64_t stride) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) off[i] = i * stride;
+}
+
+// out[d][k] = mean over chunks of part[c][d][k] (binary64 sum).
+__global__ void k_mean_chunks(const float* part, int64_t n_chunks, int n_det, int Fw, float* out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_det * Fw) return;
+  double sum = 0.0;
+  for (int64_t c = 0; c < n_chunks; ++c) sum += double(part[c * int64_t(n_det) * Fw + i]);
+  out[i] = float(sum / double(n_chunks));
+}
+
+// Truncated whitening filter of one detector, by one workgroup of NC/16
+// threads: the whitening gain g on the window grid (from the PSD row), its
+// impulse response by an inverse real transform, the cos^2 taper over
+// circular lags |n| < M/2, and the magnitude of the forward real transform.
+struct FiltArgs {
+  DevCfg cf;
+  const float* psd;  // [D][Fw]
+  float* filt;       // [D][NC + 1]
+  int M;
+  const void* tw;    // cpx<T>[NC]
+  const void* twr;   // cpx<T>[NC/2 + 1]
+};
+
+template <class T, int NC>
+__global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
+  constexpr int NT = NC / 16, LS = LdsSize<NC>::value;
+  __shared__ T lds[2 * LS];
+  T* sre = lds;
+  T* sim = lds + LS;
+  const int t = threadIdx.x;
+  const int d = blockIdx.x;
+  const DevCfg& cf = a.cf;
+  const float* psd = a.psd + int64_t(d) * cf.Fw;
+  const cpx<T>* twr = reinterpret_cast<const cpx<T>*>(a.twr);
+  PowTwiddle<T, NC, 0> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
+  uint32_t flag = 0;
+  // 1. g is real and even: pack it for the half-length inverse transform
+  for (int i = 0; i <= 8; ++i) {
+    const int k = t + NT * i;
+    if (k > NC / 2) break;
+    const int km = NC - k;
+    const cpx<T> W = twr[k];
+    const cpx<T> Yk = {whiten_gain<T>(cf, psd, k, NC, flag), T(0)};
+    const cpx<T> Ym = km == k ? Yk : cpx<T>{whiten_gain<T>(cf, psd, km, NC, flag), T(0)};
+    const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
+    const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
+    sre[lpad(k)] = p.x - q.y;
+    sim[lpad(k)] = p.y + q.x;
+    if (k != 0 && km != k) {
+      sre[lpad(km)] = p.x + q.y;
+      sim[lpad(km)] = -p.y + q.x;
+    }
+  }
+  __syncthreads();
+  cpx<T> v[16];
+  block_fft<T, NC, +1, true, 0>(v, sre, sim, t, tw);
+  // 2. v[e] holds samples 2n, 2n+1 of the response (times NC): scale and taper
+  const int N = 2 * NC;
+  const T sc = T(1) / T(NC);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int n = fft_out_index<NC, 0>(t, e);
+    T h[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int m = 2 * n + j;
+      const int lag = m <= NC ? m : m - N;
+      T sn, cs;
+      sincospi_t(T(lag) / T(a.M), &sn, &cs);
+      h[j] = 2 * abs(lag) < a.M ? cs * cs : T(0);
+    }
+    v[e] = {v[e].x * sc * h[0], v[e].y * sc * h[1]};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int i = lpad(fft_out_index<NC, 0>(t, e));
+    sre[i] = v[e].x;
+    sim[i] = v[e].y;
+  }
+  __syncthreads();
+  // 3. forward real transform of the tapered response
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = lpad(t + NT * j);
+    v[fft_in_slot<NC, 0>(j)] = {sre[i], sim[i]};
+  }
+  __syncthreads();
+  block_fft<T, NC, -1, false, 0>(v, sre, sim, t, tw);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int i = lpad(fft_out_index<NC, 0>(t, e));
+    sre[i] = v[e].x;
+    sim[i] = v[e].y;
+  }
+  __syncthreads();
+  float* out = a.filt + int64_t(d) * (NC + 1);
+  for (int i = 0; i <= 8; ++i) {
+    const int k = t + NT * i;
+    if (k > NC / 2) break;
+    const int km = NC - k;
+    const cpx<T> W = twr[k];
+    const cpx<T> A = {sre[lpad(k)], sim[lpad(k)]};
+    const cpx<T> Bm = {sre[lpad(km & (NC - 1))], sim[lpad(km & (NC - 1))]};
+    const cpx<T> s = cadd(A, cconj(Bm));
+    const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
+    out[k] = float(fabs(T(0.5) * (s.x + u.y)));
+    if (km != k) out[km] = float(fabs(T(0.5) * (s.x - u.y)));
+  }
+  (void)flag;
 }
 
 }  // namespace
@@ -475,6 +596,19 @@ static void launch_welch(const DevCfg& d, int64_t blocks, const WelchArgs& a, hi
     // binary64: one radix order, occupancy as the registers allow
     if (d.L == 2048) hipLaunchKernelGGL((k_welch<T, ACC, 2048, 0, 1>), dim3(unsigned(blocks)), dim3(128), 0, stream, a);
     else hipLaunchKernelGGL((k_welch<T, ACC, 4096, 0, 1>), dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+  }
+}
+
+template <class T>
+static void launch_filter(const DevCfg& d, const FiltArgs& a, hipStream_t stream) {
+  const dim3 grid = dim3(unsigned(d.n_det));
+  switch (d.N / 2) {
+    case 2048: hipLaunchKernelGGL((k_filter<T, 2048>), grid, dim3(128), 0, stream, a); break;
+    case 4096: hipLaunchKernelGGL((k_filter<T, 4096>), grid, dim3(256), 0, stream, a); break;
+    case 8192: hipLaunchKernelGGL((k_filter<T, 8192>), grid, dim3(512), 0, stream, a); break;
+    default:
+      if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_filter<T, 16384>), grid, dim3(1024), 0, stream, a);
+      break;
   }
 }
 
@@ -957,6 +1091,83 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
   return s;
+}
+
+// ------------------------------------------------------- per-run PSD mode
+static int64_t align256(int64_t v) { return ((v + 255) / 256) * 256; }
+
+gw_status gw_run_psd_workspace_size(const gw_ctx* c, int64_t n_chunks, int64_t* bytes) {
+  if (!c || !bytes || n_chunks < 1) return GW_EINVAL;
+  *bytes = align256(n_chunks * 8) + align256(n_chunks * c->dc.n_det * int64_t(c->dc.Fw) * 4);
+  return GW_OK;
+}
+
+gw_status gw_run_psd(gw_ctx* c, const float* bg, int64_t L_bg, int64_t n_chunks, float* psd, void* workspace,
+                     int64_t workspace_bytes, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  const DevCfg& d = c->dc;
+  if (n_chunks < 1 || n_chunks * d.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad n_chunks");
+  if (!bg || !psd || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(bg) || !aligned16(psd) || !aligned16(workspace)) return fail(c, GW_EINVAL, "misaligned pointer");
+  const int64_t stride = int64_t(d.K) * d.S;
+  if ((n_chunks - 1) * stride + d.P > L_bg) return fail(c, GW_EINVAL, "n_chunks stretches exceed the background");
+  int64_t need = 0;
+  gw_run_psd_workspace_size(c, n_chunks, &need);
+  if (workspace_bytes < need) return fail(c, GW_EINVAL, "workspace too small");
+  int64_t* off = static_cast<int64_t*>(workspace);
+  float* part = reinterpret_cast<float*>(static_cast<char*>(workspace) + align256(n_chunks * 8));
+  hipLaunchKernelGGL(k_chunk_offsets, dim3(unsigned((n_chunks + 255) / 256)), dim3(256), 0, stream, off, n_chunks,
+                     stride);
+  gw_status s = check_launch(c, "k_chunk_offsets");
+  if (s != GW_OK) return s;
+  s = welch_launch(c, bg, L_bg, off, n_chunks, part, stream);
+  if (s != GW_OK) return s;
+  const int n = d.n_det * d.Fw;
+  hipLaunchKernelGGL(k_mean_chunks, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, part, n_chunks, d.n_det,
+                     d.Fw, psd);
+  return check_launch(c, "k_mean_chunks");
+}
+
+gw_status gw_whiten_filter(gw_ctx* c, const float* psd, int64_t M, float* filt, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  const DevCfg& d = c->dc;
+  if (!psd || !filt) return fail(c, GW_EINVAL, "NULL pointer");
+  if (!aligned4(psd) || !aligned4(filt)) return fail(c, GW_EINVAL, "misaligned pointer");
+  if (M < 2 || M >= d.N || (M & 1)) return fail(c, GW_EINVAL, "M must be even with 2 <= M < N");
+  FiltArgs a{d, psd, filt, int(M), c->tw_win, c->twr_win};
+  if (d.precision == 2) launch_filter<double>(d, a, stream);
+  else launch_filter<float>(d, a, stream);
+  return check_launch(c, "k_filter");
+}
+
+gw_status gw_generate_batch_runpsd(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, const float* bg,
+                                   int64_t L_bg, const float* filt, int64_t crop, float* out, float* params_f32,
+                                   uint32_t* status, void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  gw_status s = check_batch_args(c, B, bg, L_bg, out, params_f32, status, workspace, workspace_bytes);
+  if (s != GW_OK || B == 0) return s;
+  if (!filt || !aligned4(filt)) return fail(c, GW_EINVAL, "filter NULL or misaligned");
+  if (crop < 0 || (crop & 1) || 2 * crop >= c->dc.N) return fail(c, GW_EINVAL, "crop must be even with 2 crop < N");
+  if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
+  s = enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out, params_f32, status, workspace, kStageParams,
+                    stream);
+  if (s != GW_OK) return s;
+  char* ws = static_cast<char*>(workspace);
+  WinArgs a = win_args(c);
+  a.src = bg;
+  a.L_bg = L_bg;
+  a.offset = reinterpret_cast<int64_t*>(ws + ws_params_bytes(B));
+  a.params = reinterpret_cast<double*>(ws);
+  a.B = B;
+  a.psd = filt;
+  a.out = out;
+  a.status = status;
+  char* wfp = ws + ws_params_bytes(B) + ws_offset_bytes(B) + ws_psd_bytes(c->dc, B);
+  a.wf = reinterpret_cast<const WfScalars*>(wfp);
+  a.dsc = reinterpret_cast<const DetScalars*>(wfp + ws_wf_bytes(B));
+  a.crop = int(crop);
+  launch_window_prec<4>(c->dc, B * c->dc.n_det, a, stream);
+  return check_launch(c, "k_window<per-run filter>");
 }
 
 }  // extern "C"

@@ -37,7 +37,8 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_graph_destroy", "gw_set_tuning", "gw_get_tuning", "gw_autotune",
            "gw_ragged_create", "gw_ragged_destroy", "gw_ragged_last_error", "gw_ragged_query",
            "gw_ragged_offsets", "gw_generate_ragged", "gw_ragged_graph_create",
-           "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune")
+           "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune",
+           "gw_run_psd_workspace_size", "gw_run_psd", "gw_whiten_filter", "gw_generate_batch_runpsd")
 
 TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH, RTUNE_WINDOW_MODE = 1, 2, 3, 4, 5
@@ -125,6 +126,10 @@ def lib():
             "gw_ragged_set_tuning": ([vp, i32, i64], i32),
             "gw_ragged_get_tuning": ([vp, i32, ctypes.POINTER(i64)], i32),
             "gw_ragged_autotune": ([vp, vp, vp, vp, vp, i64, i32, vp], i32),
+            "gw_run_psd_workspace_size": ([vp, i64, ctypes.POINTER(i64)], i32),
+            "gw_run_psd": ([vp, vp, i64, i64, vp, vp, i64, vp], i32),
+            "gw_whiten_filter": ([vp, vp, i64, vp, vp], i32),
+            "gw_generate_batch_runpsd": ([vp, u64, u64, i64, vp, i64, vp, i64, vp, vp, vp, vp, i64, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -333,6 +338,42 @@ class Generator:
         import torch
         n = self.workspace_size(B)
         return torch.empty((n + 7) // 8, dtype=torch.float64, device=device)
+
+    # -- per-run PSD mode -------------------------------------------------
+    def run_psd(self, bg, n_chunks, psd):
+        """Per-detector Welch PSD over the first n_chunks*K segments of bg."""
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(psd, torch.float32, (self.sizes["D"], self.sizes["Fw"]), "psd")
+        v = ctypes.c_int64()
+        self._check(lib().gw_run_psd_workspace_size(self._h, int(n_chunks), ctypes.byref(v)),
+                    "gw_run_psd_workspace_size")
+        ws = torch.empty((v.value + 7) // 8, dtype=torch.float64, device=bg.device)
+        self._check(lib().gw_run_psd(self._h, _ptr(bg), bg.shape[1], int(n_chunks), _ptr(psd), _ptr(ws),
+                                     v.value, _stream()), "gw_run_psd")
+        return ws  # keep alive until the stream has run
+
+    def whiten_filter(self, psd, M, filt):
+        import torch
+        _want(psd, torch.float32, (self.sizes["D"], self.sizes["Fw"]), "psd")
+        _want(filt, torch.float32, (self.sizes["D"], self.sizes["F"]), "filt")
+        self._check(lib().gw_whiten_filter(self._h, _ptr(psd), int(M), _ptr(filt), _stream()), "gw_whiten_filter")
+
+    def generate_batch_runpsd(self, seed, batch_index, B, bg, filt, crop, out, workspace, params_f32=None,
+                              status=None):
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(filt, torch.float32, (self.sizes["D"], self.sizes["F"]), "filt")
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"] - 2 * int(crop)), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_generate_batch_runpsd(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
+                                                   bg.shape[1], _ptr(filt), int(crop), _ptr(out),
+                                                   _ptr(params_f32), _ptr(status), _ptr(workspace), nbytes,
+                                                   _stream()), "gw_generate_batch_runpsd")
 
     # -- graphs and tuning ------------------------------------------------
     def graph(self, seed, first_batch, B, bg, out, workspace, params_f32=None, status=None):
