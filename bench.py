@@ -167,6 +167,30 @@ def surrogate_leg(gen, bg, args, K, W, dev):
 
 # ------------------------------------------------------------------- main
 
+def pairs_leg(gen, bg, args, K, W, dev):
+    """View pairs (reference and shifted view of every sample) at the
+    paper-scale shape: one prior draw and one Welch PSD per pair."""
+    import torch
+    z = gen.sizes
+    B, D, N = args.batch, z["D"], z["N"]
+    ref = torch.empty((B, D, N), dtype=torch.float32, device=dev)
+    shf = torch.empty_like(ref)
+    ws = gen.alloc_workspace(B, device=dev)
+    for i in range(W):
+        gen.generate_batch_pairs(2, i, B, bg, ref, shf, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        gen.generate_batch_pairs(2, W + i, B, bg, ref, shf, ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nbytes = B * D * (z["P"] + N + 2 * N) * 4
+    log("view pairs: %.3f ms/batch, %.0f pairs/s" % (1e3 * el / K, B * K / el))
+    return {"workload": "paper_scale view pairs (reference view at t_ref = T - 1.5 s and the shifted view)",
+            "value": round(B * K / el, 1), "unit": "pairs/s", "ms_per_step": round(1e3 * el / K, 4),
+            "hbm_frac_algorithmic": round(nbytes / (el / K) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def runpsd_leg(gen, bg, args, K, W, dev):
     """Per-run PSD mode at the paper-scale shape: one Welch PSD per detector
     over the whole background, a truncated whitening filter (fduration 2 s),
@@ -293,6 +317,7 @@ def main():
     ap.add_argument("--surrogate-batch", type=int, default=8192)
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-runpsd", action="store_true")
+    ap.add_argument("--no-pairs", action="store_true")
     ap.add_argument("--ragged-batch", type=int, default=16384)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy a buffer of this size three times "
@@ -412,6 +437,9 @@ def main():
     runpsd = None
     if not args.no_runpsd:
         runpsd = runpsd_leg(gen, bg, args, K, W, dev)
+    pairs = None
+    if not args.no_pairs:
+        pairs = pairs_leg(gen, bg, args, K, W, dev)
 
     ragged = None
     if not args.no_ragged:
@@ -462,6 +490,7 @@ def main():
         "surrogate": surrogate,
         "ragged": ragged,
         "per_run_psd": runpsd,
+        "view_pairs": pairs,
     }
     print(json.dumps(rec), flush=True)
 

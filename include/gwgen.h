@@ -233,6 +233,30 @@ gw_status gw_generate_batch_runpsd(gw_ctx* ctx, uint64_t seed, uint64_t batch_in
                                    void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Views for self-supervised pre-training and extrinsic oversampling.
+ * ------------------------------------------------------------------------ */
+/* View pairs (Fig. 2 and section 4): out_shift is exactly gw_generate_batch's
+ * output; out_ref has the same parameters, background windows and PSDs with
+ * the signal at the fixed reference time t_ref = T - 1.5 s (the start of the
+ * t_c prior), so each shifted view is its reference view with the signal
+ * delayed by t_c - t_ref in [0, 1 s).  Both float [B][n_det][N]. */
+gw_status gw_generate_batch_pairs(gw_ctx* ctx, uint64_t seed, uint64_t batch_index, int64_t B,
+                                  const float* bg, int64_t L_bg, float* out_ref, float* out_shift,
+                                  float* params_f32, uint32_t* status, void* workspace,
+                                  int64_t workspace_bytes, hipStream_t stream);
+/* gw_generate_batch with ext_k sky positions per intrinsic draw (the
+ * augmentation in the extrinsic parameters proposed in section 5): global
+ * sample g is sky position g % ext_k of intrinsic draw g / ext_k.  Every
+ * parameter row is drawn at Philox index g / ext_k; alpha, delta, psi and
+ * the background offset use the Philox sub-counter g % ext_k (the fourth
+ * counter word), the other rows sub-counter 0.  ext_k = 1 gives exactly
+ * gw_generate_batch; 1 <= ext_k <= 65536. */
+gw_status gw_generate_batch_oversampled(gw_ctx* ctx, uint64_t seed, uint64_t batch_index, int64_t B,
+                                        int32_t ext_k, const float* bg, int64_t L_bg, float* out,
+                                        float* params_f32, uint32_t* status, void* workspace,
+                                        int64_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Captured batch pipelines (HIP graphs).  A gw_graph replays the kernels of
  * one batch with the pointers given at creation; every launch then advances
  * a batch counter kept in the workspace, so replay r (counting from 0 after

@@ -15,6 +15,11 @@ Readings where the paper is silent:
     DFT coefficients);
   * injection in the time domain, y_d = bg_d[o+P : o+P+N] + irfft_N(H_d);
   * whitened output: float64 [B][D][N].
+  * view pairs for self-supervised pre-training (Fig. 2, section 4): the
+    shifted view d' is the ordinary sample; the reference view d has the
+    same parameters, background window and PSD with t_c set to the fixed
+    reference t_ref = T - 1.5 s (the start of the t_c prior), so d' is d
+    with the signal delayed by t_c - t_ref in [0, 1 s);
   * uneven batches (several window lengths and sample rates in one batch):
     slot i of a batch of B slots is an ordinary sample of its own class's
     configuration, drawn at global index batch_index * B + i with that
@@ -164,3 +169,15 @@ def generate_sample_runpsd(cfg, bg, p, offset, filt, crop):
     H = project_detectors(cfg, p, hp, hc)
     y = inject(cfg, bg, offset, H)
     return np.stack([whiten_filtered(y[d], filt[d], crop) for d in range(y.shape[0])])
+
+
+def reference_time(cfg):
+    """Fixed signal time of the reference view: the start of the t_c prior."""
+    return float(cfg["t_window"]) - 1.5
+
+
+def generate_pair(cfg, bg, p, offset):
+    """(d, d'): reference view and ordinary (shifted) view of one sample."""
+    p_ref = np.array(p, dtype=np.float64).copy()
+    p_ref[10] = reference_time(cfg)
+    return generate_sample(cfg, bg, p_ref, offset), generate_sample(cfg, bg, p, offset)

@@ -21,6 +21,14 @@ Parameter rows (binary64, [12][B]):
   0 M_c [Msun]  1 q = m2/m1  2 chi1  3 chi2  4 D_L [Mpc]  5 iota  6 alpha
   7 delta  8 psi  9 phi_c  10 t_c [s]  11 reserved (0)
 Philox stream ids: the row index for rows 0-10, 12 for the offset.
+
+Extrinsic oversampling (the augmentation the paper's discussion of
+sky-location recovery proposes: several sky positions per intrinsic draw):
+with k sky positions per intrinsic draw, global sample index g belongs to
+intrinsic draw g // k and is its (g % k)-th sky position.  Every row is
+drawn at counter index g // k; rows alpha, delta, psi and the background
+offset use the Philox sub-counter g % k, the others sub-counter 0.  k = 1
+gives the ordinary draws.
 """
 
 import math
@@ -35,11 +43,14 @@ N_PARAMS = 12
 OFFSET_STREAM = 12
 
 
-def sample_params(cfg, seed, first_index, B, L_bg):
+SKY_STREAMS = (6, 7, 8, OFFSET_STREAM)
+
+
+def sample_params(cfg, seed, first_index, B, L_bg, ext_k=1):
     """Draw B samples; returns (params float64 [12][B], offsets int64 [B]).
 
     cfg keys used: mc, q, chi, dl (each a (lo, hi) pair), t_window,
-    psd_length, fs.
+    psd_length, fs.  ext_k: sky positions per intrinsic draw (see above).
     """
     fs = float(cfg["fs"])
     T = float(cfg["t_window"])
@@ -48,13 +59,16 @@ def sample_params(cfg, seed, first_index, B, L_bg):
     span = L_bg - P - N + 1
     if span <= 0:
         raise ValueError("background shorter than one PSD stretch plus window")
+    if ext_k < 1:
+        raise ValueError("ext_k must be positive")
     params = np.zeros((N_PARAMS, B), dtype=np.float64)
     offsets = np.zeros(B, dtype=np.int64)
     (mc_a, mc_b), (q_a, q_b) = cfg["mc"], cfg["q"]
     (chi_a, chi_b), (dl_a, dl_b) = cfg["chi"], cfg["dl"]
     for i in range(B):
         g = first_index + i
-        u = [philox_uniform(seed, g, s) for s in range(11)]
+        gi, j = g // ext_k, g % ext_k
+        u = [philox_uniform(seed, gi, s, j if s in SKY_STREAMS else 0) for s in range(11)]
         params[0, i] = mc_a + u[0] * (mc_b - mc_a)
         params[1, i] = q_a + u[1] * (q_b - q_a)
         params[2, i] = chi_a + u[2] * (chi_b - chi_a)
@@ -69,6 +83,6 @@ def sample_params(cfg, seed, first_index, B, L_bg):
         params[8, i] = math.pi * u[8]
         params[9, i] = 2.0 * math.pi * u[9]
         params[10, i] = T - 1.5 + u[10] * 1.0
-        uo = philox_uniform(seed, g, OFFSET_STREAM)
+        uo = philox_uniform(seed, gi, OFFSET_STREAM, j)
         offsets[i] = int(math.floor(uo * span))
     return params, offsets

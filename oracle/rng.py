@@ -7,9 +7,10 @@ definition.  The HIP side carries its own implementation; the two agree bit
 for bit, and this one is pinned to the published known-answer vectors.
 
 Counter layout for prior draws: key = (seed & 0xffffffff, seed >> 32),
-counter = (index & 0xffffffff, index >> 32, stream, 0), where index is the
+counter = (index & 0xffffffff, index >> 32, stream, sub), where index is the
 global sample index (batch_index * B + i), so a run's output does not depend
-on how it is split into batches.
+on how it is split into batches.  sub is 0 except for the extrinsic draws of
+oversampled batches (the j-th sky position of an intrinsic draw uses j).
 
 Uniform in the open interval (0, 1) from the first two output words a, b:
 u = ((a >> 5) * 2**26 + (b >> 6) + 0.5) * 2**-53, exact in binary64.
@@ -42,12 +43,12 @@ def philox4x32_10(ctr, key):
     return ctr
 
 
-def philox_uniform(seed, index, stream):
-    """One binary64 uniform in (0, 1) for (seed, global sample index, stream)."""
+def philox_uniform(seed, index, stream, sub=0):
+    """One binary64 uniform in (0, 1) for (seed, global sample index, stream, sub)."""
     seed = int(seed)
     index = int(index)
     a, b, _, _ = philox4x32_10(
-        (index & MASK32, (index >> 32) & MASK32, int(stream), 0),
+        (index & MASK32, (index >> 32) & MASK32, int(stream), int(sub)),
         (seed & MASK32, (seed >> 32) & MASK32))
     return ((a >> 5) * 67108864 + (b >> 6) + 0.5) * 2.0 ** -53
 

@@ -15,15 +15,21 @@ namespace gw {
 // Prior draws for global sample index g (the densities of Table 1 with the
 // ranges in c), the window's background offset in [0, span), status
 // initialisation, and the per-sample constants of the fused window kernel.
-// Row 11 of the parameters receives p11.
+// Row 11 of the parameters receives p11.  With ext_k sky positions per
+// intrinsic draw, g is sky position g % ext_k of intrinsic draw g / ext_k:
+// every row is drawn at counter index g / ext_k, and alpha, delta, psi and
+// the offset use the sub-counter g % ext_k (ext_k = 1: ordinary draws).
 __device__ __forceinline__ void draw_sample(const DevCfg& c, uint64_t seed, uint64_t g, int64_t i, int64_t B,
                                             int64_t span, double p11, double* params, int64_t* offset,
-                                            float* params_f32, uint32_t* status, WfScalars* wf, DetScalars* dsc) {
+                                            float* params_f32, uint32_t* status, WfScalars* wf, DetScalars* dsc,
+                                            uint32_t ext_k = 1u) {
 #pragma clang fp contract(off)
+  const uint64_t gi = g / ext_k;
+  const uint32_t j = uint32_t(g - gi * ext_k);
   double u[11];
 #pragma unroll
-  for (int s = 0; s < 11; ++s) u[s] = philox_uniform(seed, g, uint32_t(s));
-  const double uo = philox_uniform(seed, g, 12u);
+  for (int s = 0; s < 11; ++s) u[s] = philox_uniform(seed, gi, uint32_t(s), (s >= 6 && s <= 8) ? j : 0u);
+  const double uo = philox_uniform(seed, gi, 12u, j);
   double p[12];
   p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
   p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
@@ -96,6 +102,8 @@ struct WinArgs {
   const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
   float logmm_max;        // fallback threshold (SRC 3)
   int crop;               // samples dropped at each end of the output (SRC 4; even)
+  int ref_view;           // SRC 1: signal at t_ref instead of the sample's t_c
+  double t_ref;
 };
 
 // Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
@@ -228,6 +236,9 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
     cxx = T(dsh.fx * wsh.cosi);
     tauT = dsh.tau * cf.invT;
+    if constexpr (SRC == 1) {
+      if (a.ref_view) tauT = (dsh.tau - wsh.tc + a.t_ref) * cf.invT;  // same delays, signal at t_ref
+    }
   }
   const float2* hsrc = reinterpret_cast<const float2*>(hrow);
 

@@ -89,8 +89,9 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 }
 
 // binary64 uniform in (0, 1) from the first two words
-__device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t index, uint32_t stream) {
-  U4 o = philox4x32_10(U4{uint32_t(index), uint32_t(index >> 32), stream, 0u},
+__device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t index, uint32_t stream,
+                                                 uint32_t sub = 0u) {
+  U4 o = philox4x32_10(U4{uint32_t(index), uint32_t(index >> 32), stream, sub},
                        uint32_t(seed), uint32_t(seed >> 32));
   return (double(o.a >> 5) * 67108864.0 + double(o.b >> 6) + 0.5) * 0x1p-53;
 }

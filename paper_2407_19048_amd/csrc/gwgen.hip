@@ -43,6 +43,7 @@ struct SampleArgs {
   uint32_t* status;
   WfScalars* wf;     // [B] waveform constants for the fused kernel, or NULL
   DetScalars* dsc;   // [B][D] antenna patterns and delays, or NULL
+  uint32_t ext_k = 1;  // sky positions per intrinsic draw
 };
 
 __global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_sample_params(SampleArgs a) {
   if (i >= a.B) return;
   const uint64_t first = a.batch ? *a.batch * uint64_t(a.B) : a.first;
   draw_sample(a.cf, a.seed, first + uint64_t(i), i, a.B, a.span, 0.0, a.params, a.offset, a.params_f32, a.status,
-              a.wf, a.dsc);
+              a.wf, a.dsc, a.ext_k);
 }
 
 // -------------------------------------------------------- plus / cross
@@ -648,7 +649,8 @@ static gw_status check_batch_args(gw_ctx* c, int64_t B, const float* bg, int64_t
 // batch index at run time for graph replays.
 static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, const uint64_t* batch, int64_t B,
                                const float* bg, int64_t L_bg, float* out, float* params_f32, uint32_t* status,
-                               void* workspace, int stages, hipStream_t stream) {
+                               void* workspace, int stages, hipStream_t stream, uint32_t ext_k = 1,
+                               float* out_ref = nullptr) {
   const int64_t span = L_bg - c->dc.P - c->dc.N + 1;
   char* ws = static_cast<char*>(workspace);
   double* params = reinterpret_cast<double*>(ws);
@@ -658,7 +660,8 @@ static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, c
   DetScalars* dsc = reinterpret_cast<DetScalars*>(reinterpret_cast<char*>(wf) + ws_wf_bytes(B));
   gw_status s = GW_OK;
   if (stages & kStageParams) {
-    SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), batch, B, span, params, offset, params_f32, status, wf, dsc};
+    SampleArgs sa{c->dc, seed, batch_index * uint64_t(B), batch, B, span, params, offset, params_f32, status, wf, dsc,
+                  ext_k};
     hipLaunchKernelGGL(k_sample_params, dim3(unsigned((B + 255) / 256)), dim3(256), 0, stream, sa);
     s = check_launch(c, "k_sample_params");
     if (s != GW_OK) return s;
@@ -681,6 +684,14 @@ static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, c
     a.dsc = dsc;
     launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
     s = check_launch(c, "k_window<fused>");
+    if (s == GW_OK && out_ref) {
+      // reference view: same windows, PSDs and parameters, signal at t_ref
+      a.out = out_ref;
+      a.ref_view = 1;
+      a.t_ref = c->dc.T - 1.5;
+      launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
+      s = check_launch(c, "k_window<reference view>");
+    }
   }
   return s;
 }
@@ -1168,6 +1179,32 @@ gw_status gw_generate_batch_runpsd(gw_ctx* c, uint64_t seed, uint64_t batch_inde
   a.crop = int(crop);
   launch_window_prec<4>(c->dc, B * c->dc.n_det, a, stream);
   return check_launch(c, "k_window<per-run filter>");
+}
+
+// ------------------------------------------- view pairs and oversampling
+gw_status gw_generate_batch_pairs(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, const float* bg,
+                                  int64_t L_bg, float* out_ref, float* out_shift, float* params_f32, uint32_t* status,
+                                  void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  gw_status s = check_batch_args(c, B, bg, L_bg, out_shift, params_f32, status, workspace, workspace_bytes);
+  if (s != GW_OK || B == 0) return s;
+  if (!out_ref || !aligned16(out_ref)) return fail(c, GW_EINVAL, "out_ref NULL or misaligned");
+  if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
+  return enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out_shift, params_f32, status, workspace, kStageAll,
+                       stream, 1u, out_ref);
+}
+
+gw_status gw_generate_batch_oversampled(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, int32_t ext_k,
+                                        const float* bg, int64_t L_bg, float* out, float* params_f32,
+                                        uint32_t* status, void* workspace, int64_t workspace_bytes,
+                                        hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (ext_k < 1 || ext_k > 65536) return fail(c, GW_EINVAL, "ext_k must be in 1..65536");
+  gw_status s = check_batch_args(c, B, bg, L_bg, out, params_f32, status, workspace, workspace_bytes);
+  if (s != GW_OK || B == 0) return s;
+  if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
+  return enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out, params_f32, status, workspace, kStageAll,
+                       stream, uint32_t(ext_k));
 }
 
 }  // extern "C"

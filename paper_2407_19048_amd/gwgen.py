@@ -38,7 +38,8 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_ragged_create", "gw_ragged_destroy", "gw_ragged_last_error", "gw_ragged_query",
            "gw_ragged_offsets", "gw_generate_ragged", "gw_ragged_graph_create",
            "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune",
-           "gw_run_psd_workspace_size", "gw_run_psd", "gw_whiten_filter", "gw_generate_batch_runpsd")
+           "gw_run_psd_workspace_size", "gw_run_psd", "gw_whiten_filter", "gw_generate_batch_runpsd",
+           "gw_generate_batch_pairs", "gw_generate_batch_oversampled")
 
 TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH, RTUNE_WINDOW_MODE = 1, 2, 3, 4, 5
@@ -130,6 +131,8 @@ def lib():
             "gw_run_psd": ([vp, vp, i64, i64, vp, vp, i64, vp], i32),
             "gw_whiten_filter": ([vp, vp, i64, vp, vp], i32),
             "gw_generate_batch_runpsd": ([vp, u64, u64, i64, vp, i64, vp, i64, vp, vp, vp, vp, i64, vp], i32),
+            "gw_generate_batch_pairs": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp, vp, i64, vp], i32),
+            "gw_generate_batch_oversampled": ([vp, u64, u64, i64, i32, vp, i64, vp, vp, vp, vp, i64, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -338,6 +341,38 @@ class Generator:
         import torch
         n = self.workspace_size(B)
         return torch.empty((n + 7) // 8, dtype=torch.float64, device=device)
+
+    # -- view pairs and oversampling ---------------------------------------
+    def generate_batch_pairs(self, seed, batch_index, B, bg, out_ref, out_shift, workspace, params_f32=None,
+                             status=None):
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        for t, nm in ((out_ref, "out_ref"), (out_shift, "out_shift")):
+            _want(t, torch.float32, (B, self.sizes["D"], self.sizes["N"]), nm)
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_generate_batch_pairs(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
+                                                  bg.shape[1], _ptr(out_ref), _ptr(out_shift), _ptr(params_f32),
+                                                  _ptr(status), _ptr(workspace), nbytes, _stream()),
+                    "gw_generate_batch_pairs")
+
+    def generate_batch_oversampled(self, seed, batch_index, B, ext_k, bg, out, workspace, params_f32=None,
+                                   status=None):
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(lib().gw_generate_batch_oversampled(self._h, int(seed), int(batch_index), int(B), int(ext_k),
+                                                        _ptr(bg), bg.shape[1], _ptr(out), _ptr(params_f32),
+                                                        _ptr(status), _ptr(workspace), nbytes, _stream()),
+                    "gw_generate_batch_oversampled")
 
     # -- per-run PSD mode -------------------------------------------------
     def run_psd(self, bg, n_chunks, psd):

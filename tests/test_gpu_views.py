@@ -1,0 +1,107 @@
+"""View pairs and extrinsic oversampling through the C ABI against the
+oracle (whitened relative L2 per window <= 1e-5, params relative error <=
+1e-12, offsets exact)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pipeline, priors
+from paper_2407_19048_amd import gwgen, inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+_BG = {}
+
+
+def bg_for(name, log2):
+    key = (name, log2)
+    if key not in _BG:
+        cfg = inputs.config(name)
+        _BG[key] = inputs.background(len(cfg["det_ids"]), 1 << log2, cfg["fs"], seed=1)
+    return _BG[key]
+
+
+@pytest.mark.parametrize("name", ["pr1_plain", "paper_scale"])
+def test_view_pairs_match_oracle(name):
+    cfg = inputs.config(name)
+    bg_np = bg_for(name, 21)
+    gen = gwgen.Generator(cfg)
+    B, D, N = 8, gen.sizes["D"], gen.sizes["N"]
+    bg = torch.from_numpy(bg_np).to(DEV)
+    ref_t = torch.empty((B, D, N), dtype=torch.float32, device=DEV)
+    shf_t = torch.empty_like(ref_t)
+    ws = gen.alloc_workspace(B)
+    _say("view pairs %s" % name)
+    gen.generate_batch_pairs(6, 2, B, bg, ref_t, shf_t, ws)
+    plain = torch.empty_like(ref_t)
+    ws2 = gen.alloc_workspace(B)
+    gen.generate_batch(6, 2, B, bg, plain, ws2)
+    torch.cuda.synchronize()
+    # the shifted view is the ordinary batch, bit for bit
+    assert torch.equal(shf_t, plain)
+    p, o = priors.sample_params(cfg, 6, 2 * B, B, bg_np.shape[1])
+    got_ref, got_shf = ref_t.cpu().numpy(), shf_t.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        d_ref, d_shf = pipeline.generate_pair(cfg, bg_np, p[:, i], int(o[i]))
+        for d in range(D):
+            e = max(rel_l2(got_ref[i, d], d_ref[d]), rel_l2(got_shf[i, d], d_shf[d]))
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("view pairs worst rel L2 %.3e" % worst)
+
+
+@pytest.mark.parametrize("ext_k", [1, 4])
+def test_oversampled_batch_matches_oracle(ext_k):
+    cfg = inputs.config("paper_scale")
+    bg_np = bg_for("paper_scale", 21)
+    gen = gwgen.Generator(cfg)
+    B, D, N = 12, gen.sizes["D"], gen.sizes["N"]
+    bg = torch.from_numpy(bg_np).to(DEV)
+    out = torch.empty((B, D, N), dtype=torch.float32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("oversampled ext_k=%d" % ext_k)
+    gen.generate_batch_oversampled(8, 3, B, ext_k, bg, out, ws)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    params, offs = params.cpu().numpy(), offs.cpu().numpy()
+    p, o = priors.sample_params(cfg, 8, 3 * B, B, bg_np.shape[1], ext_k=ext_k)
+    np.testing.assert_allclose(params, p, rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(offs, o)
+    g = out.cpu().numpy()
+    for i in range(0, B, 3):
+        ref = pipeline.generate_sample(cfg, bg_np, p[:, i], int(o[i]))
+        for d in range(D):
+            assert rel_l2(g[i, d], ref[d]) <= 1e-5, (i, d)
+    if ext_k == 1:
+        plain = torch.empty_like(out)
+        gen.generate_batch(8, 3, B, bg, plain, gen.alloc_workspace(B))
+        torch.cuda.synchronize()
+        assert torch.equal(plain, out)
+
+
+def test_oversampling_rejects_bad_k():
+    cfg = inputs.config("pr1_plain")
+    gen = gwgen.Generator(cfg)
+    bg = torch.zeros((2, 1 << 20), dtype=torch.float32, device=DEV)
+    out = torch.empty((2, 2, gen.sizes["N"]), dtype=torch.float32, device=DEV)
+    with pytest.raises(gwgen.GWError):
+        gen.generate_batch_oversampled(1, 0, 2, 0, bg, out, gen.alloc_workspace(2))
