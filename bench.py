@@ -167,6 +167,35 @@ def surrogate_leg(gen, bg, args, K, W, dev):
 
 # ------------------------------------------------------------------- main
 
+def burst_leg(bg, args, K, W, dev):
+    """Sine-Gaussian bursts at the paper-scale shape (same background, Welch
+    and whitening; the waveform family changes)."""
+    import torch
+    from paper_2407_19048_amd import gwgen, inputs
+    cfg = inputs.config("sine_gaussian", precision=args.precision)
+    gen = gwgen.Generator(cfg)
+    z = gen.sizes
+    B = args.batch
+    out = torch.empty((B, z["D"], z["N"]), dtype=torch.float32, device=dev)
+    ws = gen.alloc_workspace(B, device=dev)
+    gen.autotune(B, bg, out, ws, reps=2)
+    graph = gen.graph(2, 0, B, bg, out, ws)
+    for _ in range(W):
+        graph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        graph.launch()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    graph.close()
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("non-finite burst output")
+    log("sine-Gaussian: %.3f ms/batch, %.0f samples/s" % (1e3 * el / K, B * K / el))
+    return {"workload": "sine-Gaussian bursts, paper-scale shape (f0 32-1000 Hz, Q 3-30, hrss 1e-23-1e-21)",
+            "value": round(B * K / el, 1), "unit": "samples/s", "ms_per_step": round(1e3 * el / K, 4)}
+
+
 def pairs_leg(gen, bg, args, K, W, dev):
     """View pairs (reference and shifted view of every sample) at the
     paper-scale shape: one prior draw and one Welch PSD per pair."""
@@ -318,6 +347,7 @@ def main():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-runpsd", action="store_true")
     ap.add_argument("--no-pairs", action="store_true")
+    ap.add_argument("--no-burst", action="store_true")
     ap.add_argument("--ragged-batch", type=int, default=16384)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy a buffer of this size three times "
@@ -440,6 +470,9 @@ def main():
     pairs = None
     if not args.no_pairs:
         pairs = pairs_leg(gen, bg, args, K, W, dev)
+    burst = None
+    if not args.no_burst:
+        burst = burst_leg(bg, args, K, W, dev)
 
     ragged = None
     if not args.no_ragged:
@@ -491,6 +524,7 @@ def main():
         "ragged": ragged,
         "per_run_psd": runpsd,
         "view_pairs": pairs,
+        "sine_gaussian": burst,
     }
     print(json.dumps(rec), flush=True)
 

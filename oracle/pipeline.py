@@ -31,7 +31,7 @@ import numpy as np
 from .detectors import antenna_patterns, detector_geometry, time_delays
 from .priors import sample_params
 from .spectral import interp_psd, run_psd, truncated_filter, welch_psd, whiten, whiten_filtered
-from .waveform import fd_waveform
+from .waveform import fd_waveform, sine_gaussian
 
 
 def derived_sizes(cfg):
@@ -52,8 +52,12 @@ def fd_grid(cfg):
 def waveform_on_grid(cfg, p):
     """h+, hx on the window grid for one parameter column p (len 12)."""
     f = fd_grid(cfg)
-    hp, hc = fd_waveform(f, int(cfg["approximant"]), p[0], p[1], p[2], p[3],
-                         p[4], p[5], p[9], float(cfg["f_min"]))
+    if int(cfg["approximant"]) == 2:
+        # rows: 0 f0, 1 Q, 2 hrss, 5 iota, 9 phi0
+        hp, hc = sine_gaussian(f, p[0], p[1], p[2], p[5], p[9], float(cfg["f_min"]))
+    else:
+        hp, hc = fd_waveform(f, int(cfg["approximant"]), p[0], p[1], p[2], p[3],
+                             p[4], p[5], p[9], float(cfg["f_min"]))
     hp[0] = hc[0] = 0.0
     hp[-1] = hc[-1] = 0.0
     return hp, hc

@@ -20,6 +20,9 @@ Readings where the paper is silent:
 Parameter rows (binary64, [12][B]):
   0 M_c [Msun]  1 q = m2/m1  2 chi1  3 chi2  4 D_L [Mpc]  5 iota  6 alpha
   7 delta  8 psi  9 phi_c  10 t_c [s]  11 reserved (0)
+For the sine-Gaussian burst (approximant 2): 0 f0 [Hz] uniform, 1 Q
+uniform, 2 hrss log-uniform, 3 and 4 zero, rows 5-10 as above (9 is the
+burst phase phi0, 10 its peak time t0); ranges from cfg f0, quality, hrss.
 Philox stream ids: the row index for rows 0-10, 12 for the offset.
 
 Extrinsic oversampling (the augmentation the paper's discussion of
@@ -69,12 +72,18 @@ def sample_params(cfg, seed, first_index, B, L_bg, ext_k=1):
         g = first_index + i
         gi, j = g // ext_k, g % ext_k
         u = [philox_uniform(seed, gi, s, j if s in SKY_STREAMS else 0) for s in range(11)]
-        params[0, i] = mc_a + u[0] * (mc_b - mc_a)
-        params[1, i] = q_a + u[1] * (q_b - q_a)
-        params[2, i] = chi_a + u[2] * (chi_b - chi_a)
-        params[3, i] = chi_a + u[3] * (chi_b - chi_a)
-        # uniform in volume: CDF (D^3 - a^3) / (b^3 - a^3)
-        params[4, i] = (dl_a ** 3 + u[4] * (dl_b ** 3 - dl_a ** 3)) ** (1.0 / 3.0)
+        if int(cfg.get("approximant", 0)) == 2:
+            (f_a, f_b), (Q_a, Q_b), (h_a, h_b) = cfg["f0"], cfg["quality"], cfg["hrss"]
+            params[0, i] = f_a + u[0] * (f_b - f_a)
+            params[1, i] = Q_a + u[1] * (Q_b - Q_a)
+            params[2, i] = math.exp(math.log(h_a) + u[2] * (math.log(h_b) - math.log(h_a)))
+        else:
+            params[0, i] = mc_a + u[0] * (mc_b - mc_a)
+            params[1, i] = q_a + u[1] * (q_b - q_a)
+            params[2, i] = chi_a + u[2] * (chi_b - chi_a)
+            params[3, i] = chi_a + u[3] * (chi_b - chi_a)
+            # uniform in volume: CDF (D^3 - a^3) / (b^3 - a^3)
+            params[4, i] = (dl_a ** 3 + u[4] * (dl_b ** 3 - dl_a ** 3)) ** (1.0 / 3.0)
         # sine density on (0, pi): cos(iota) uniform on (-1, 1)
         params[5, i] = math.acos(2.0 * u[5] - 1.0)
         params[6, i] = 2.0 * math.pi * u[6]

@@ -41,6 +41,18 @@ IMR-form (approximant 1), a closed-form inspiral-merger-ringdown model:
   A(f_t)(f/f_t)^(-2/3) on [f_t, f_RD); then that value at f_RD times the
   Lorentzian f_damp^2/((f-f_RD)^2 + f_damp^2).  Cut-off f < 0.2/M.
 
+Sine-Gaussian burst (approximant 2; the burst morphology section 7 names as
+an extension), central frequency f0, quality Q, root-sum-square strain hrss,
+inclination-like polarisation angle iota, phase phi0, peak at t0 = 0:
+  h+(t) = A (1 + cos^2 iota)/2 exp(-t^2/tau^2) cos(2 pi f0 t + phi0)
+  hx(t) = A cos(iota) exp(-t^2/tau^2) sin(2 pi f0 t + phi0)
+  tau = Q / (sqrt(2) pi f0),  A = S hrss / sqrt(tau sqrt(pi/2))
+(so that the integral of h+^2 + hx^2 is (S hrss)^2 at iota = 0).  With
+G(x) = (sqrt(pi) tau / 2) exp(-pi^2 tau^2 x^2) the transform is
+  h+ = A (1 + cos^2 iota)/2 [e^{i phi0} G(f - f0) + e^{-i phi0} G(f + f0)]
+  hx = A cos(iota) [-i e^{i phi0} G(f - f0) + i e^{-i phi0} G(f + f0)]
+nonzero for f >= f_min, f > 0 (no cut-off).
+
 Pins: the TaylorF2 phase is tied to the post-Newtonian energy and flux
 through the stationary-phase relation dPsi/df = 2 pi t(f); the amplitude to
 the stationary-phase transform of the quadrupole chirp; the remnant and
@@ -176,6 +188,21 @@ def imr_form_model(f, mc, q, chi1, chi2, dl):
                    np.where(f < f_rd, A_t * (f / f_t) ** (-2.0 / 3.0),
                             A_rd * f_damp ** 2 / ((f - f_rd) ** 2 + f_damp ** 2)))
     return amp, phase
+
+
+def sine_gaussian(f, f0, Q, hrss, iota, phi0, f_min):
+    """(h+, hx) complex128 of the sine-Gaussian burst on frequencies f (t0 = 0)."""
+    f = np.asarray(f, dtype=np.float64)
+    tau = Q / (math.sqrt(2.0) * math.pi * f0)
+    A = STRAIN_SCALE * hrss / math.sqrt(tau * math.sqrt(math.pi / 2.0))
+    G = lambda x: 0.5 * math.sqrt(math.pi) * tau * np.exp(-(math.pi * tau * x) ** 2)
+    em = np.exp(1j * phi0) * G(f - f0)
+    ep = np.exp(-1j * phi0) * G(f + f0)
+    ci = math.cos(iota)
+    band = (f >= f_min) & (f > 0)
+    hp = np.where(band, A * 0.5 * (1.0 + ci * ci) * (em + ep), 0.0)
+    hc = np.where(band, A * ci * (-1j * em + 1j * ep), 0.0)
+    return hp.astype(np.complex128), hc.astype(np.complex128)
 
 
 def frequency_cutoff(approximant, mc, q):

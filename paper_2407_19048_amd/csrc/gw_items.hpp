@@ -31,12 +31,21 @@ __device__ __forceinline__ void draw_sample(const DevCfg& c, uint64_t seed, uint
   for (int s = 0; s < 11; ++s) u[s] = philox_uniform(seed, gi, uint32_t(s), (s >= 6 && s <= 8) ? j : 0u);
   const double uo = philox_uniform(seed, gi, 12u, j);
   double p[12];
-  p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
-  p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
-  p[2] = c.chi[0] + u[2] * (c.chi[1] - c.chi[0]);
-  p[3] = c.chi[0] + u[3] * (c.chi[1] - c.chi[0]);
-  const double a3 = c.dl[0] * c.dl[0] * c.dl[0], b3 = c.dl[1] * c.dl[1] * c.dl[1];
-  p[4] = pow(a3 + u[4] * (b3 - a3), 1.0 / 3.0);
+  if (c.approximant == 2) {
+    // sine-Gaussian: f0 and Q uniform, hrss log-uniform
+    p[0] = c.f0r[0] + u[0] * (c.f0r[1] - c.f0r[0]);
+    p[1] = c.Qr[0] + u[1] * (c.Qr[1] - c.Qr[0]);
+    p[2] = exp(log(c.hrssr[0]) + u[2] * (log(c.hrssr[1]) - log(c.hrssr[0])));
+    p[3] = 0.0;
+    p[4] = 0.0;
+  } else {
+    p[0] = c.mc[0] + u[0] * (c.mc[1] - c.mc[0]);
+    p[1] = c.q[0] + u[1] * (c.q[1] - c.q[0]);
+    p[2] = c.chi[0] + u[2] * (c.chi[1] - c.chi[0]);
+    p[3] = c.chi[0] + u[3] * (c.chi[1] - c.chi[0]);
+    const double a3 = c.dl[0] * c.dl[0] * c.dl[0], b3 = c.dl[1] * c.dl[1] * c.dl[1];
+    p[4] = pow(a3 + u[4] * (b3 - a3), 1.0 / 3.0);
+  }
   p[5] = acos(2.0 * u[5] - 1.0);
   p[6] = 2.0 * kPi * u[6];
   p[7] = asin(2.0 * u[7] - 1.0);
@@ -52,9 +61,14 @@ __device__ __forceinline__ void draw_sample(const DevCfg& c, uint64_t seed, uint
     for (int r = 0; r < 12; ++r) params_f32[r * B + i] = float(p[r]);
   }
   if (status) {
-    const double eta = p[1] / ((1.0 + p[1]) * (1.0 + p[1]));
-    const double Ms = p[0] * pow(eta, -0.6) * kMsunSec;
-    const double f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
+    double f_cut;
+    if (c.approximant == 2) {
+      f_cut = p[0] + 5.0 / (kPi * (p[1] / (sqrt(2.0) * kPi * p[0])));  // f0 + 5/(pi tau)
+    } else {
+      const double eta = p[1] / ((1.0 + p[1]) * (1.0 + p[1]));
+      const double Ms = p[0] * pow(eta, -0.6) * kMsunSec;
+      f_cut = c.approximant == 0 ? 1.0 / (pow(6.0, 1.5) * kPi * Ms) : 0.2 / Ms;
+    }
     status[i] = f_cut > 0.5 * c.fs ? GW_STATUS_CUT_AT_NYQUIST : 0u;
   }
   if (wf) {
@@ -132,10 +146,27 @@ __device__ __forceinline__ T filter_gain(const float* filt, int k, uint32_t& fla
 }
 
 // Projected signal (DFT coefficients) at window bin k, generated in registers.
+// Projected sine-Gaussian at bin k: fs sg_G0 [G(f - f0)(cpl - i cxx) e^{-2 pi i rm}
+// + G(f + f0)(cpl + i cxx) e^{-2 pi i rp}], rm/rp = k tau/T -/+ phi0/(2 pi).
+template <class T, class TP>
+__device__ __forceinline__ cpx<T> burst_bin(const DevCfg& cf, const WfScalars& w, T cpl, T cxx, double tauT, int k) {
+  const double f = double(k) * cf.invT;
+  const T xm = T(f - w.sg_f0), xp = T(f + w.sg_f0);
+  const T gm = exp(-T(w.sg_pt2) * xm * xm), gp = exp(-T(w.sg_pt2) * xp * xp);
+  const TP base = frac1(TP(k) * TP(tauT));
+  T sm, cm, sp, cp;
+  sincos_rev(T(frac1(base - TP(w.sg_rphi))), &sm, &cm);
+  sincos_rev(T(frac1(base + TP(w.sg_rphi))), &sp, &cp);
+  const T A = T(cf.fs) * T(w.sg_G0);
+  return {A * (gm * (cpl * cm - cxx * sm) + gp * (cpl * cp + cxx * sp)),
+          A * (gp * (cxx * cp - cpl * sp) - gm * (cpl * sm + cxx * cm))};
+}
+
 template <class T, class TP, bool FULL>
 __device__ __forceinline__ cpx<T> signal_bin(const DevCfg& cf, const WinArgs& a, const WfScalars& w, T cpl, T cxx,
                                              double tauT, int k) {
   if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
+  if (cf.approximant == 2) return burst_bin<T, TP>(cf, w, cpl, cxx, tauT, k);
   const double kc = a.kcbrt[k], lk = a.lnk3[k];
   TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
   rev = frac1(rev);

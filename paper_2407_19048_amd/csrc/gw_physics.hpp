@@ -71,6 +71,7 @@ struct DevCfg {
   int occ_welch;           // waves per SIMD the Welch kernel is compiled for (2 or 3)
   double fs, T, invT, f_min, inv_ratio;
   double mc[2], q[2], chi[2], dl[2];
+  double f0r[2], Qr[2], hrssr[2];  // sine-Gaussian prior ranges (approximant 2)
   DetGeom det[4];
 };
 
@@ -108,6 +109,8 @@ struct WfScalars {
   double At, Ard, ft, fdamp2;
   double Apl;           // At (f_t T)^(2/3): power-law amplitude Apl k^(-2/3) between f_t and f_RD
   double cN;            // Newtonian phase in revolutions at bin k: cN k^(-5/3)
+  // sine-Gaussian (approximant 2): G(x) = sg_G0 exp(-sg_pt2 x^2), phase phi0 / (2 pi)
+  double sg_f0, sg_pt2, sg_G0, sg_rphi;
   int kend, kt, krd;    // band end; first bins with f >= f_t and f >= f_RD
   int cut_nyquist;
   double cosi, tc, ra, dec, psi;
@@ -166,6 +169,25 @@ __device__ __forceinline__ void tf2_phase_and_slope(double f, double Ms, double 
 
 __device__ __forceinline__ void wf_setup(const double* __restrict__ params, int64_t B, int64_t b,
                                          const DevCfg& cf, WfScalars& w) {
+  if (cf.approximant == 2) {
+    // sine-Gaussian: rows 0 f0, 1 Q, 2 hrss, 5 iota, 9 phi0, 10 t0
+    const double f0 = params[0 * B + b], Q = params[1 * B + b], hrss = params[2 * B + b];
+    w.ra = params[6 * B + b];
+    w.dec = params[7 * B + b];
+    w.psi = params[8 * B + b];
+    w.tc = params[10 * B + b];
+    w.cosi = cos(params[5 * B + b]);
+    const double tau = Q / (sqrt(2.0) * kPi * f0);
+    const double A = kStrainScale * hrss / sqrt(tau * sqrt(0.5 * kPi));
+    w.sg_f0 = f0;
+    w.sg_pt2 = kPi * kPi * tau * tau;
+    w.sg_G0 = A * 0.5 * sqrt(kPi) * tau;
+    w.sg_rphi = params[9 * B + b] / (2.0 * kPi);
+    w.kend = cf.N / 2;
+    w.kt = w.krd = w.kend;
+    w.cut_nyquist = f0 + 5.0 / (kPi * tau) >= 0.5 * cf.fs ? 1 : 0;
+    return;
+  }
   const double mc = params[0 * B + b], q = params[1 * B + b];
   const double chi1 = params[2 * B + b], chi2 = params[3 * B + b];
   const double dl = params[4 * B + b], iota = params[5 * B + b];

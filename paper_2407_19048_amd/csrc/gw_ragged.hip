@@ -326,7 +326,9 @@ bool same_shared_fields(const gw_config& a, const gw_config& b) {
   for (int d = 0; d < a.n_det; ++d)
     if (a.det_id[d] != b.det_id[d]) return false;
   for (int i = 0; i < 2; ++i)
-    if (a.mc[i] != b.mc[i] || a.q[i] != b.q[i] || a.chi[i] != b.chi[i] || a.dl[i] != b.dl[i]) return false;
+    if (a.mc[i] != b.mc[i] || a.q[i] != b.q[i] || a.chi[i] != b.chi[i] || a.dl[i] != b.dl[i] ||
+        a.f0[i] != b.f0[i] || a.quality[i] != b.quality[i] || a.hrss[i] != b.hrss[i])
+      return false;
   return true;
 }
 

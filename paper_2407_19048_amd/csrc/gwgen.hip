@@ -74,7 +74,19 @@ __global__ __launch_bounds__(256) void k_gen_fd_waveform(WaveArgs a) {
   const int F = a.cf.F;
   for (int k = threadIdx.x; k < F; k += 256) {
     float2 hp = {0.f, 0.f}, hc = {0.f, 0.f};
-    if (k > 0 && k >= a.cf.kmin && k < w.kend) {
+    if (k > 0 && k >= a.cf.kmin && k < w.kend && a.cf.approximant == 2) {
+      // sine-Gaussian: h+ = ap [e^{i phi0} G(f - f0) + e^{-i phi0} G(f + f0)],
+      // hx = ax [-i e^{i phi0} G(f - f0) + i e^{-i phi0} G(f + f0)]
+      const double f = double(k) * a.cf.invT;
+      const TP xm = TP(f - w.sg_f0), xp = TP(f + w.sg_f0);
+      const TP gm = TP(w.sg_G0) * exp(-TP(w.sg_pt2) * xm * xm), gp = TP(w.sg_G0) * exp(-TP(w.sg_pt2) * xp * xp);
+      TP sp, cp;
+      sincos_rev(TP(w.sg_rphi), &sp, &cp);
+      const TP emx = gm * cp, emy = gm * sp, epx = gp * cp, epy = -gp * sp;
+      const TP ap = TP(0.5) * (TP(1) + TP(w.cosi) * TP(w.cosi)), ax = TP(w.cosi);
+      hp = {float(ap * (emx + epx)), float(ap * (emy + epy))};
+      hc = {float(ax * (emy - epy)), float(ax * (epx - emx))};
+    } else if (k > 0 && k >= a.cf.kmin && k < w.kend) {
       const double kc = a.kcbrt[k], lk = a.lnk3[k];
       TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, a.cf.invT) + TP(w.pconst);
       rev = frac1(rev);
@@ -470,12 +482,19 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   if (P < L || (P - L) % S) return bad("psd_length*fs - L must be a non-negative multiple of the stride");
   if (N % L) return bad("t_window must be a whole multiple of fftlen");
   if (!(g->f_min >= 0) || !(g->f_min < 0.5 * g->fs)) return bad("f_min must be in [0, fs/2)");
-  if (g->approximant < 0 || g->approximant > 1) return bad("approximant must be 0 or 1");
+  if (g->approximant < 0 || g->approximant > 2) return bad("approximant must be 0, 1 or 2");
+  if (g->approximant == 2) {
+    if (!(g->f0[0] > 0) || !(g->f0[1] >= g->f0[0]) || !(g->f0[1] < 0.5 * g->fs)) return bad("bad f0 range");
+    if (!(g->quality[0] > 0) || !(g->quality[1] >= g->quality[0])) return bad("bad quality range");
+    if (!(g->hrss[0] > 0) || !(g->hrss[1] >= g->hrss[0])) return bad("bad hrss range");
+  }
   if (g->precision < 0 || g->precision > 2) return bad("precision must be 0, 1 or 2");
-  if (!(g->mc[0] > 0) || !(g->mc[1] >= g->mc[0])) return bad("bad chirp-mass range");
-  if (!(g->q[0] > 0) || !(g->q[1] >= g->q[0]) || g->q[1] > 1) return bad("bad mass-ratio range (0 < q <= 1)");
-  if (!(g->chi[0] > -1) || !(g->chi[1] < 1) || !(g->chi[1] >= g->chi[0])) return bad("bad spin range (|chi| < 1)");
-  if (!(g->dl[0] > 0) || !(g->dl[1] >= g->dl[0])) return bad("bad distance range");
+  if (g->approximant != 2) {
+    if (!(g->mc[0] > 0) || !(g->mc[1] >= g->mc[0])) return bad("bad chirp-mass range");
+    if (!(g->q[0] > 0) || !(g->q[1] >= g->q[0]) || g->q[1] > 1) return bad("bad mass-ratio range (0 < q <= 1)");
+    if (!(g->chi[0] > -1) || !(g->chi[1] < 1) || !(g->chi[1] >= g->chi[0])) return bad("bad spin range (|chi| < 1)");
+    if (!(g->dl[0] > 0) || !(g->dl[1] >= g->dl[0])) return bad("bad distance range");
+  }
   if (g->precision == 2 && N > 16384) return GW_EUNSUPPORTED;
   DevCfg c;
   std::memset(&c, 0, sizeof(c));
@@ -502,6 +521,9 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
     c.q[i] = g->q[i];
     c.chi[i] = g->chi[i];
     c.dl[i] = g->dl[i];
+    c.f0r[i] = g->f0[i];
+    c.Qr[i] = g->quality[i];
+    c.hrssr[i] = g->hrss[i];
   }
   // first bin with k/T >= f_min (k/T rounded as the binary64 grid is formed)
   int k = int(std::ceil(g->f_min * g->t_window));

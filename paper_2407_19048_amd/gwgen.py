@@ -54,7 +54,9 @@ class GWConfig(ctypes.Structure):
                 ("overlap", ctypes.c_double), ("f_min", ctypes.c_double),
                 ("approximant", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mc", ctypes.c_double * 2), ("q", ctypes.c_double * 2),
-                ("chi", ctypes.c_double * 2), ("dl", ctypes.c_double * 2)]
+                ("chi", ctypes.c_double * 2), ("dl", ctypes.c_double * 2),
+                ("f0", ctypes.c_double * 2), ("quality", ctypes.c_double * 2),
+                ("hrss", ctypes.c_double * 2)]
 
 
 _LIB = None
@@ -156,6 +158,10 @@ def make_config(cfg):
     for name in ("mc", "q", "chi", "dl"):
         arr = getattr(c, name)
         arr[0], arr[1] = float(cfg[name][0]), float(cfg[name][1])
+    for name in ("f0", "quality", "hrss"):
+        arr = getattr(c, name)
+        lo, hi = cfg.get(name, (0.0, 0.0))
+        arr[0], arr[1] = float(lo), float(hi)
     return c
 
 

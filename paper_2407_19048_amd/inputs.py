@@ -42,6 +42,10 @@ CONFIGS = {
         mc=(10.0, 100.0), q=(0.125, 1.0), chi=(-0.99, 0.99), dl=(100.0, 3100.0),
         batch=2048, log2_bg=27),
 }
+# sine-Gaussian bursts at the paper-scale shape (f0, Q, hrss ranges: a
+# reading; the paper only names the morphology)
+CONFIGS["sine_gaussian"] = dict(CONFIGS["paper_scale"], approximant=2, f0=(32.0, 1000.0), quality=(3.0, 30.0),
+                                hrss=(1e-23, 1e-21))
 CONFIGS["precision_study"] = dict(CONFIGS["paper_scale"], batch=8192)
 CONFIGS["surrogate"] = dict(CONFIGS["paper_scale"], batch=8192)
 

@@ -41,8 +41,9 @@ def test_strerror():
 
 
 def test_config_struct_layout():
-    # int32 n_det, int32[4], pad, 6 doubles, 2 int32, 8 doubles
-    assert ctypes.sizeof(gwgen.GWConfig) == 4 + 16 + 4 + 48 + 8 + 64
+    # int32 n_det, int32[4], pad, 6 doubles, 2 int32, 8 doubles, 6 doubles
+    assert ctypes.sizeof(gwgen.GWConfig) == 4 + 16 + 4 + 48 + 8 + 64 + 48
+    assert gwgen.GWConfig.f0.offset == 4 + 16 + 4 + 48 + 8 + 64
 
 
 def _create(cfg):

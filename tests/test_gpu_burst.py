@@ -1,0 +1,123 @@
+"""Sine-Gaussian burst workload through the C ABI against the oracle: every
+step (h+ relative L2 <= 1e-5 over the band, whitened strain <= 1e-5 per
+window, PSD RMS ratio error <= 1e-4), the fused batch, and a ragged batch of
+burst classes."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pipeline
+from paper_2407_19048_amd import gwgen, inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+_BG = {}
+
+
+def bg_for(fs, log2):
+    key = (fs, log2)
+    if key not in _BG:
+        _BG[key] = inputs.background(3, 1 << log2, fs, seed=1)
+    return _BG[key]
+
+
+def test_burst_stages_match_oracle():
+    cfg = inputs.config("sine_gaussian")
+    bg_np = bg_for(2048.0, 21)
+    gen = gwgen.Generator(cfg)
+    z = gen.sizes
+    B = 6
+    bg = torch.from_numpy(bg_np).to(DEV)
+    params = torch.empty((12, B), dtype=torch.float64, device=DEV)
+    offs = torch.empty(B, dtype=torch.int64, device=DEV)
+    gen.sample_params(4, 10, B, bg_np.shape[1], params, offs)
+    hp = torch.empty((B, z["F"]), dtype=torch.complex64, device=DEV)
+    hc = torch.empty_like(hp)
+    gen.gen_fd_waveform(params, hp, hc)
+    hdet = torch.empty((B, 3, z["F"]), dtype=torch.complex64, device=DEV)
+    gen.project_detectors(params, hp, hc, hdet)
+    strain = torch.empty((B, 3, z["N"]), dtype=torch.float32, device=DEV)
+    gen.inject(bg, offs, hdet, strain)
+    psd = torch.empty((B, 3, z["Fw"]), dtype=torch.float32, device=DEV)
+    gen.welch_psd(bg, offs, psd)
+    out = torch.empty_like(strain)
+    gen.whiten(strain, psd, out)
+    torch.cuda.synchronize()
+    p_ref, o_ref = oracle.sample_params(cfg, 4, 10, B, bg_np.shape[1])
+    P, O = params.cpu().numpy(), offs.cpu().numpy()
+    np.testing.assert_allclose(P, p_ref, rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(O, o_ref)
+    HP, HC, HD, OUT = hp.cpu().numpy(), hc.cpu().numpy(), hdet.cpu().numpy(), out.cpu().numpy()
+    for i in range(B):
+        ref, st = pipeline.generate_sample(cfg, bg_np, p_ref[:, i], int(o_ref[i]), return_stages=True)
+        assert rel_l2(HP[i], st["hp"]) <= 1e-5 and rel_l2(HC[i], st["hc"]) <= 1e-5, i
+        assert rel_l2(HD[i], st["H"]) <= 1e-5, i
+        for d in range(3):
+            assert rel_l2(OUT[i, d], ref[d]) <= 1e-5, (i, d)
+            assert math.sqrt(np.mean((psd[i, d].cpu().numpy() / st["psd"][d] - 1) ** 2)) <= 1e-4
+
+
+@pytest.mark.parametrize("B,log2,check", [(16, 21, None), (2048, 22, (0, 1000, 2047))])
+def test_burst_fused_batch_matches_oracle(B, log2, check):
+    cfg = inputs.config("sine_gaussian")
+    bg_np = bg_for(2048.0, log2)
+    gen = gwgen.Generator(cfg)
+    out = torch.empty((B, 3, gen.sizes["N"]), dtype=torch.float32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("burst fused B=%d" % B)
+    gen.generate_batch(2, 0, B, torch.from_numpy(bg_np).to(DEV), out, ws)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    worst = 0.0
+    for i in (range(B) if check is None else check):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        for d in range(3):
+            e = rel_l2(G[i, d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("burst worst rel L2 %.3e" % worst)
+
+
+def test_burst_ragged_classes_match_oracle():
+    classes = [dict(c, approximant=2, f0=(32.0, 500.0), quality=(3.0, 30.0), hrss=(1e-23, 1e-21))
+               for c in inputs.ragged_classes()[:3]]  # 1024 Hz: 4, 8, 16 s
+    cls = np.array([0, 1, 2, 2, 1, 0], dtype=np.int32)
+    bg_np = bg_for(1024.0, 20)
+    rg = gwgen.Ragged(classes, cls)
+    bg = torch.from_numpy(bg_np).to(DEV)
+    out, ws = rg.alloc_out(), rg.alloc_workspace()
+    rg.generate(3, 1, [bg, bg, bg], out, ws)
+    torch.cuda.synchronize()
+    po, oo = pipeline.ragged_draws(classes, cls, 3, 1, [bg_np.shape[1]] * 3)
+    for i in range(len(cls)):
+        c = int(cls[i])
+        ref = pipeline.generate_sample(classes[c], bg_np, po[:, i], int(oo[i]))
+        got = rg.signal(out, i).cpu().numpy()
+        for d in range(3):
+            assert rel_l2(got[d], ref[d]) <= 1e-5, (i, d)
+
+
+def test_burst_config_validation():
+    bad = dict(inputs.config("sine_gaussian"), f0=(32.0, 1500.0))  # above fs/2
+    with pytest.raises(gwgen.GWError):
+        gwgen.Generator(bad)
