@@ -167,6 +167,40 @@ def surrogate_leg(gen, bg, args, K, W, dev):
 
 # ------------------------------------------------------------------- main
 
+def long_leg(bg, args, K, W, dev):
+    """Long-duration binary neutron stars: 256 s windows at 2048 Hz (N = 2^19),
+    batch 256; the window transforms run as four-step FFTs through HBM."""
+    import torch
+    from paper_2407_19048_amd import gwgen, inputs
+    cfg = inputs.config("bns_long", precision=args.precision)
+    gen = gwgen.Generator(cfg)
+    z = gen.sizes
+    B = cfg["batch"]
+    out = torch.empty((B, z["D"], z["N"]), dtype=torch.float32, device=dev)
+    ws = gen.alloc_workspace(B, device=dev)
+    graph = gen.graph(2, 0, B, bg, out, ws)
+    for _ in range(W):
+        graph.launch()
+    torch.cuda.synchronize()
+    Kl = max(1, K // 5)
+    t0 = time.perf_counter()
+    for _ in range(Kl):
+        graph.launch()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    graph.close()
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("non-finite long-window output")
+    nbytes = B * z["D"] * (z["P"] + 2 * z["N"]) * 4
+    gbs = nbytes / (el / Kl) / 1e9
+    log("long windows: %.3f ms/batch of %d, %.0f samples/s, %.0f GB/s algorithmic"
+        % (1e3 * el / Kl, B, B * Kl / el, gbs))
+    return {"workload": "long-duration BNS: batch %d, 256 s windows at 2048 Hz (N = 2^19), TaylorF2, "
+                        "Welch over the preceding 64 s" % B,
+            "value": round(B * Kl / el, 1), "unit": "samples/s", "ms_per_step": round(1e3 * el / Kl, 4),
+            "steps": Kl, "hbm_frac_algorithmic": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def burst_leg(bg, args, K, W, dev):
     """Sine-Gaussian bursts at the paper-scale shape (same background, Welch
     and whitening; the waveform family changes)."""
@@ -348,6 +382,7 @@ def main():
     ap.add_argument("--no-runpsd", action="store_true")
     ap.add_argument("--no-pairs", action="store_true")
     ap.add_argument("--no-burst", action="store_true")
+    ap.add_argument("--no-long", action="store_true")
     ap.add_argument("--ragged-batch", type=int, default=16384)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="after the timed region, copy a buffer of this size three times "
@@ -473,6 +508,9 @@ def main():
     burst = None
     if not args.no_burst:
         burst = burst_leg(bg, args, K, W, dev)
+    longw = None
+    if not args.no_long:
+        longw = long_leg(bg, args, K, W, dev)
 
     ragged = None
     if not args.no_ragged:
@@ -525,6 +563,7 @@ def main():
         "per_run_psd": runpsd,
         "view_pairs": pairs,
         "sine_gaussian": burst,
+        "long_windows": longw,
     }
     print(json.dumps(rec), flush=True)
 

@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(_HERE, "csrc", n) for n in ("gwgen.hip", "gw_ragged.hip", "gw_surrogate.hip")]
+SRCS = [os.path.join(_HERE, "csrc", n) for n in ("gwgen.hip", "gw_ragged.hip", "gw_long.hip", "gw_surrogate.hip")]
 OUT = os.path.join(_HERE, "libgwgen.so")
 
 HIPCC_FLAGS = [

@@ -17,6 +17,7 @@ struct gw_ctx {
   void* tw_win = nullptr;     // cpx<T>[N/2]
   void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
   void* tw_welch = nullptr;   // cpx<T>[L]
+  void* tw_long = nullptr;    // cpx<float>[N/2] for windows longer than 32768 samples
   std::string err;
 };
 
@@ -29,7 +30,12 @@ struct gw_graph {
 };
 
 namespace gw {
+struct WinArgs;
 gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg);
+// Window stage of windows longer than 32768 samples (four-step transforms
+// in the output buffer): src 0 whiten, 1 fused batch, 2 inject.
+gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, const float* hdet, int64_t items,
+                      hipStream_t st);
 gw_status ctx_check_launch(gw_ctx* c, const char* what);
 // Host validation of a configuration into device constants (nothing launched).
 gw_status validate_config(const gw_config* g, DevCfg* dc, std::string* why);

@@ -1,0 +1,283 @@
+// Long windows (N > 32768 samples, e.g. long-duration binary-neutron-star
+// signals): the half-length complex transform of NC = N/2 points no longer
+// fits in one workgroup's LDS and runs as a four-step FFT through HBM, with
+// NC = N1 x N2, N1 = 16384 (one workgroup transform in LDS) and N2 = NC/N1
+// in {2, 4, 8, 16, 32} (in registers).  With c[m] = y[2m] + i y[2m+1]:
+//
+//   forward  columns  w[k2][m1] = W_NC^(m1 k2) sum_m2 c[m1 + N1 m2] W_N2^(m2 k2)
+//            rows     X[k2 + N2 k1] = sum_m1 w[k2][m1] W_N1^(m1 k1)   (in place)
+//   bins     real-spectrum unpack of the pair (k, NC - k), in-register
+//            signal, whitening, repack for the inverse (in place, on the
+//            transposed layout X'[k2][k1] = X[k2 + N2 k1])
+//   inverse  rows     u[k2][m1] = sum_k1 Z[k2 + N2 k1] W_N1^(-m1 k1)  (in place)
+//            columns  c[m1 + N1 m2] = (1/NC) sum_k2 W_N2^(-m2 k2) W_NC^(-m1 k2) u[k2][m1]
+//
+// The thread of column m1 reads u[k2][m1] for every k2 and writes
+// c[m1 + N1 m2] for every m2: the same complex positions, so the inverse
+// also runs in place.  Every pass works inside the caller's output buffer
+// (N floats = NC complex per window); no other memory is needed.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "gw_fft.hpp"
+#include "gw_physics.hpp"
+#include "gw_internal.hpp"
+#include "gw_items.hpp"
+#include "../../include/gwgen.h"
+
+using namespace gw;
+
+namespace {
+
+constexpr int kN1 = 16384;
+
+// In-register DFT of length R (natural order in and out), DIR = -1 forward.
+template <int R, int DIR, class T>
+__device__ __forceinline__ void dft_small(cpx<T>* a) {
+  if constexpr (R == 2) dft2<DIR>(a);
+  else if constexpr (R == 4) dft4<DIR>(a);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else if constexpr (R == 16) dft16<DIR>(a);
+  else {
+    static_assert(R == 32, "N2 in {2, 4, 8, 16, 32}");
+    cpx<T> e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      e[i] = a[2 * i];
+      o[i] = a[2 * i + 1];
+    }
+    dft16<DIR>(e);
+    dft16<DIR>(o);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      T s, c;
+      sincospi_t(T(2 * k) / T(32), &s, &c);  // exp(DIR 2 pi i k / 32)
+      const cpx<T> w = {c, T(DIR) * s};
+      const cpx<T> t = cmul(o[k], w);
+      a[k] = cadd(e[k], t);
+      a[k + 16] = csub(e[k], t);
+    }
+  }
+}
+
+struct LongArgs {
+  WinArgs w;           // cf, tables, per-sample data, psd, status; out = the in-place buffer
+  const void* twn;     // cpx<float>[NC]: exp(-2 pi i n / NC)
+  const void* twr;     // cpx<float>[NC/2 + 1]: exp(-2 pi i k / N)
+  const void* tw1;     // cpx<float>[N1]: exp(-2 pi i n / N1)
+  const float* x;      // real input of the forward columns (strain rows or the background)
+  int NC, N2, l2n2;    // NC = N1 N2, l2n2 = log2(N2)
+};
+
+// x row of window item bd (SRC 0: strain [B][D][N]; SRC 1, 2: background at o + P)
+template <int SRC>
+__device__ __forceinline__ const float* long_input(const LongArgs& a, int64_t bd) {
+  const DevCfg& cf = a.w.cf;
+  const int64_t b = bd / cf.n_det;
+  const int d = int(bd - b * cf.n_det);
+  if constexpr (SRC == 0) return a.x + bd * int64_t(cf.N);
+  else return a.x + int64_t(d) * a.w.L_bg + load_const(a.w.offset + b) + cf.P;
+}
+
+// Forward columns: one thread per column m1, grid (N1/256, B*D).
+template <int N2, int SRC>
+__global__ __launch_bounds__(256) void k_long_cols_fwd(LongArgs a) {
+  const int m1 = blockIdx.x * 256 + threadIdx.x;
+  const int64_t bd = blockIdx.y;
+  const float* x = long_input<SRC>(a, bd);
+  float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * a.NC;
+  const cpx<float>* twn = reinterpret_cast<const cpx<float>*>(a.twn);
+  cpx<float> v[N2];
+#pragma unroll
+  for (int m2 = 0; m2 < N2; ++m2) {
+    float2 q;
+    __builtin_memcpy(&q, x + 2 * (int64_t(m1) + int64_t(kN1) * m2), sizeof(q));
+    v[m2] = {q.x, q.y};
+  }
+  dft_small<N2, -1>(v);
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) {
+    const cpx<float> w = k2 ? cmul(v[k2], twn[(m1 * k2) & (a.NC - 1)]) : v[k2];
+    buf[int64_t(k2) * kN1 + m1] = {w.x, w.y};
+  }
+}
+
+// Inverse columns: twiddle, inverse DFT over k2, scale 1/NC, store real
+// samples in place; SRC 2 adds the noise window.
+template <int N2, int SRC>
+__global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
+  const int m1 = blockIdx.x * 256 + threadIdx.x;
+  const int64_t bd = blockIdx.y;
+  float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * a.NC;
+  const cpx<float>* twn = reinterpret_cast<const cpx<float>*>(a.twn);
+  cpx<float> v[N2];
+#pragma unroll
+  for (int k2 = 0; k2 < N2; ++k2) {
+    const float2 q = buf[int64_t(k2) * kN1 + m1];
+    const cpx<float> u = {q.x, q.y};
+    v[k2] = k2 ? twmul<+1>(u, twn[(m1 * k2) & (a.NC - 1)]) : u;
+  }
+  dft_small<N2, +1>(v);
+  const float sc = 1.f / float(a.NC);
+  const float* nz = nullptr;
+  if constexpr (SRC == 2) nz = long_input<2>(a, bd);
+#pragma unroll
+  for (int m2 = 0; m2 < N2; ++m2) {
+    const int64_t m = int64_t(m1) + int64_t(kN1) * m2;
+    float2 y = {v[m2].x * sc, v[m2].y * sc};
+    if constexpr (SRC == 2) {
+      y.x += nz[2 * m];
+      y.y += nz[2 * m + 1];
+    }
+    buf[m] = y;
+  }
+}
+
+// Row transforms of length N1 in place: grid B*D*N2 workgroups of N1/16.
+template <int DIR>
+__global__ __launch_bounds__(kN1 / 16) void k_long_rows(LongArgs a) {
+  constexpr int NT = kN1 / 16, LS = LdsSize<kN1>::value;
+  __shared__ float lds[2 * LS];
+  const int t = threadIdx.x;
+  float2* row = reinterpret_cast<float2*>(a.w.out) + int64_t(blockIdx.x) * kN1;
+  PowTwiddle<float, kN1, 0> tw{reinterpret_cast<const cpx<float>*>(a.tw1)};
+  cpx<float> v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const float2 q = row[t + NT * j];
+    v[fft_in_slot<kN1, 0>(j)] = {q.x, q.y};
+  }
+  block_fft<float, kN1, DIR, false, 0>(v, lds, lds + LS, t, tw);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) row[fft_out_index<kN1, 0>(t, e)] = {v[e].x, v[e].y};
+}
+
+// Bins: one thread per pair (k, NC - k), k in [0, NC/2]; grid
+// (ceil((NC/2 + 1)/256), B*D).  SRC 0 whitens, SRC 1 adds the in-register
+// signal and whitens, SRC 2 packs the given projected spectrum (inject).
+template <class TP, int SRC>
+__global__ __launch_bounds__(256) void k_long_bins(LongArgs a, const float* hdet) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int64_t bd = blockIdx.y;
+  const DevCfg& cf = a.w.cf;
+  const int NC = a.NC, N2 = a.N2;
+  __shared__ uint32_t sflag;
+  if (threadIdx.x == 0) sflag = 0u;
+  __syncthreads();
+  if (k <= NC / 2) {
+    const int64_t b = bd / cf.n_det;
+    const int d = int(bd - b * cf.n_det);
+    float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
+    const int km = NC - k;
+    // X[kk] sits at X'[kk mod N2][kk / N2]
+    auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
+    const cpx<float> W = reinterpret_cast<const cpx<float>*>(a.twr)[k];  // exp(-2 pi i k / N)
+    uint32_t flag = 0;
+    cpx<float> Yk, Ym;
+    if constexpr (SRC == 2) {
+      const float2* h = reinterpret_cast<const float2*>(hdet) + bd * (NC + 1);
+      const float2 h0 = h[k], h1 = h[km];
+      Yk = {h0.x, k == 0 ? 0.f : h0.y};
+      Ym = {h1.x, k == 0 ? 0.f : h1.y};
+    } else {
+      const float2 qa = buf[pos(k)], qb = buf[pos(km)];
+      const cpx<float> A = {qa.x, qa.y}, Bm = {qb.x, qb.y};
+      const cpx<float> s = cadd(A, cconj(Bm));
+      const cpx<float> u = cmul(W, csub(A, cconj(Bm)));
+      cpx<float> Xk = {0.5f * (s.x + u.y), 0.5f * (s.y - u.x)};
+      cpx<float> Xm = {0.5f * (s.x - u.y), 0.5f * (-s.y - u.x)};
+      if constexpr (SRC == 1) {
+        const WfScalars wsh = load_const(a.w.wf + b);
+        const DetScalars dsh = load_const(a.w.dsc + (b * cf.n_det + d));
+        const float cpl = float(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
+        const float cxx = float(dsh.fx * wsh.cosi);
+        const double tauT = dsh.tau * cf.invT;
+        Xk = cadd(Xk, signal_bin<float, TP, false>(cf, a.w, wsh, cpl, cxx, tauT, k));
+        if (km != k) Xm = cadd(Xm, signal_bin<float, TP, false>(cf, a.w, wsh, cpl, cxx, tauT, km));
+      }
+      const float* psd = a.w.psd + bd * cf.Fw;
+      Yk = cscale(Xk, whiten_gain<float>(cf, psd, k, NC, flag));
+      Ym = cscale(Xm, whiten_gain<float>(cf, psd, km, NC, flag));
+      if (km == k) Ym = Yk;
+    }
+    const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
+    const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W);
+    buf[pos(k)] = {p.x - q.y, p.y + q.x};
+    if (k != 0 && km != k) buf[pos(km)] = {p.x + q.y, -p.y + q.x};
+    if (flag) atomicOr(&sflag, flag);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sflag && a.w.status) atomicOr(a.w.status + bd / cf.n_det, sflag);
+}
+
+template <int SRC>
+void launch_cols_fwd(const LongArgs& a, int64_t items, hipStream_t st) {
+  const dim3 grid(unsigned(kN1 / 256), unsigned(items));
+  switch (a.N2) {
+    case 2: hipLaunchKernelGGL((k_long_cols_fwd<2, SRC>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_long_cols_fwd<4, SRC>), grid, dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_long_cols_fwd<8, SRC>), grid, dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_long_cols_fwd<16, SRC>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_long_cols_fwd<32, SRC>), grid, dim3(256), 0, st, a); break;
+  }
+}
+
+template <int SRC>
+void launch_cols_inv(const LongArgs& a, int64_t items, hipStream_t st) {
+  const dim3 grid(unsigned(kN1 / 256), unsigned(items));
+  switch (a.N2) {
+    case 2: hipLaunchKernelGGL((k_long_cols_inv<2, SRC>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_long_cols_inv<4, SRC>), grid, dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_long_cols_inv<8, SRC>), grid, dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_long_cols_inv<16, SRC>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_long_cols_inv<32, SRC>), grid, dim3(256), 0, st, a); break;
+  }
+}
+
+}  // namespace
+
+namespace gw {
+
+// The window stage for N > 32768: SRC 0 whitens strain rows x, SRC 1 is the
+// fused batch (x = background), SRC 2 injects hdet into the background
+// noise.  w.out is [items][N] and doubles as the transform buffer.
+gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, const float* hdet, int64_t items,
+                      hipStream_t st) {
+  const DevCfg& d = c->dc;
+  LongArgs a;
+  a.w = w;
+  a.twn = c->tw_long;
+  a.twr = c->twr_win;
+  a.tw1 = c->tw_win;
+  a.x = x;
+  a.NC = d.N / 2;
+  a.N2 = a.NC / kN1;
+  a.l2n2 = 0;
+  while ((1 << a.l2n2) < a.N2) ++a.l2n2;
+  if (items <= 0) return GW_OK;
+  if (items > 65535) return ctx_fail(c, GW_EINVAL, "long windows: at most 65535 (sample, detector) items per call");
+  const dim3 bins_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
+  const dim3 rows_grid(unsigned(items * a.N2));
+  if (src == 2) {
+    hipLaunchKernelGGL((k_long_bins<double, 2>), bins_grid, dim3(256), 0, st, a, hdet);
+    hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
+    launch_cols_inv<2>(a, items, st);
+    return ctx_check_launch(c, "long inject");
+  }
+  if (src == 0) launch_cols_fwd<0>(a, items, st);
+  else launch_cols_fwd<1>(a, items, st);
+  hipLaunchKernelGGL((k_long_rows<-1>), rows_grid, dim3(kN1 / 16), 0, st, a);
+  if (src == 0) {
+    hipLaunchKernelGGL((k_long_bins<double, 0>), bins_grid, dim3(256), 0, st, a, nullptr);
+  } else if (d.precision == 0) {
+    hipLaunchKernelGGL((k_long_bins<float, 1>), bins_grid, dim3(256), 0, st, a, nullptr);
+  } else {
+    hipLaunchKernelGGL((k_long_bins<double, 1>), bins_grid, dim3(256), 0, st, a, nullptr);
+  }
+  hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
+  launch_cols_inv<0>(a, items, st);
+  return ctx_check_launch(c, "long window");
+}
+
+}  // namespace gw

@@ -527,7 +527,7 @@ gw_status gw_ragged_create(const gw_config* classes, int32_t n_classes, const in
     if (validate_config(&classes[c], &r->dc[c], &why) != GW_OK) return bail(GW_EINVAL);
     r->cfg[c] = classes[c];
     const DevCfg& d = r->dc[c];
-    if (d.precision == 2) return bail(GW_EUNSUPPORTED);
+    if (d.precision == 2 || d.N > 32768) return bail(GW_EUNSUPPORTED);
     if (d.N < 2 * d.L) return bail(GW_EINVAL);
     if (!same_shared_fields(classes[0], classes[c])) return bail(GW_EINVAL);
     r->welch_norm[c] = 1.0 / (double(d.K) * d.fs * (3.0 * d.L / 8.0));

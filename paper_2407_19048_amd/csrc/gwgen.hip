@@ -476,7 +476,9 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   if (!integral(Nd) || !integral(Pd) || !integral(Ld) || !integral(Sd))
     return bad("t_window, psd_length, fftlen and overlap must be whole numbers of samples");
   const int64_t N = std::llround(Nd), P = std::llround(Pd), L = std::llround(Ld), S = std::llround(Sd);
-  if (!is_pow2(N) || N < 2048 || N > 32768) return bad("N = t_window*fs must be a power of two in [2048, 32768]");
+  if (!is_pow2(N) || N < 2048 || N > (int64_t(1) << 20))
+    return bad("N = t_window*fs must be a power of two in [2048, 2^20]");
+  if (N > 32768 && g->precision == 2) return GW_EUNSUPPORTED;
   if (!is_pow2(L) || L < 2048 || L > 4096) return bad("L = fftlen*fs must be 2048 or 4096");
   if (S * 2 != L) return bad("overlap must be half of fftlen (stride L/2)");
   if (P < L || (P - L) % S) return bad("psd_length*fs - L must be a non-negative multiple of the stride");
@@ -704,6 +706,10 @@ static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, c
     a.status = status;
     a.wf = wf;
     a.dsc = dsc;
+    if (c->dc.N > 32768) {
+      if (out_ref) return fail(c, GW_EUNSUPPORTED, "view pairs need N <= 32768");
+      return long_window(c, 1, a, bg, nullptr, B * c->dc.n_det, stream);
+    }
     launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
     s = check_launch(c, "k_window<fused>");
     if (s == GW_OK && out_ref) {
@@ -743,6 +749,7 @@ gw_status gw_destroy(gw_ctx* c) {
   (void)hipFree(c->tw_win);
   (void)hipFree(c->twr_win);
   (void)hipFree(c->tw_welch);
+  (void)hipFree(c->tw_long);
   delete c;
   return GW_OK;
 }
@@ -781,9 +788,12 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
     if (s == GW_OK) s = upload_twiddles<double>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<double>(c, &c->tw_welch, dc.L, dc.L);
   } else {
-    s = upload_twiddles<float>(c, &c->tw_win, NC, NC);
+    // windows longer than 32768 samples transform rows of 16384 (four-step)
+    const int NCt = NC > 16384 ? 16384 : NC;
+    s = upload_twiddles<float>(c, &c->tw_win, NCt, NCt);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->tw_welch, dc.L, dc.L);
+    if (s == GW_OK && NC > 16384) s = upload_twiddles<float>(c, &c->tw_long, NC, NC);
   }
   if (s != GW_OK) {
     gw_destroy(c);
@@ -877,6 +887,7 @@ gw_status inject(gw_ctx* c, const float* bg, int64_t L_bg, const int64_t* offset
   a.L_bg = L_bg;
   a.offset = offset;
   a.out = strain;
+  if (c->dc.N > 32768) return long_window(c, 2, a, bg, hdet, B * c->dc.n_det, stream);
   launch_window_prec<2>(c->dc, B * c->dc.n_det, a, stream);
   return check_launch(c, "k_window<inject>");
 }
@@ -910,6 +921,7 @@ gw_status whiten(gw_ctx* c, const float* strain, const float* psd, int64_t B, fl
   a.psd = psd;
   a.out = out;
   a.status = status;
+  if (c->dc.N > 32768) return long_window(c, 0, a, strain, nullptr, B * c->dc.n_det, stream);
   launch_window_prec<0>(c->dc, B * c->dc.n_det, a, stream);
   return check_launch(c, "k_window<whiten>");
 }
@@ -930,6 +942,7 @@ gw_status gw_generate_batch_surrogate(gw_ctx* c, gw_surrogate* sg, uint64_t seed
   GW_CHECK_CTX(c);
   if (!sg) return fail(c, GW_EINVAL, "surrogate is NULL");
   if (c->dc.approximant != 1) return fail(c, GW_EUNSUPPORTED, "the surrogate models approximant 1");
+  if (c->dc.N > 32768) return fail(c, GW_EUNSUPPORTED, "the surrogate batch needs N <= 32768");
   if (B < 0 || B * c->dc.n_det >= kMaxBlocks) return fail(c, GW_EINVAL, "bad B");
   if (B == 0) return GW_OK;
   if (!bg || !out || !workspace) return fail(c, GW_EINVAL, "NULL pointer");
@@ -1167,6 +1180,7 @@ gw_status gw_whiten_filter(gw_ctx* c, const float* psd, int64_t M, float* filt, 
   if (!psd || !filt) return fail(c, GW_EINVAL, "NULL pointer");
   if (!aligned4(psd) || !aligned4(filt)) return fail(c, GW_EINVAL, "misaligned pointer");
   if (M < 2 || M >= d.N || (M & 1)) return fail(c, GW_EINVAL, "M must be even with 2 <= M < N");
+  if (d.N > 32768) return fail(c, GW_EUNSUPPORTED, "the per-run filter needs N <= 32768");
   FiltArgs a{d, psd, filt, int(M), c->tw_win, c->twr_win};
   if (d.precision == 2) launch_filter<double>(d, a, stream);
   else launch_filter<float>(d, a, stream);
@@ -1180,6 +1194,7 @@ gw_status gw_generate_batch_runpsd(gw_ctx* c, uint64_t seed, uint64_t batch_inde
   gw_status s = check_batch_args(c, B, bg, L_bg, out, params_f32, status, workspace, workspace_bytes);
   if (s != GW_OK || B == 0) return s;
   if (!filt || !aligned4(filt)) return fail(c, GW_EINVAL, "filter NULL or misaligned");
+  if (c->dc.N > 32768) return fail(c, GW_EUNSUPPORTED, "the per-run mode needs N <= 32768");
   if (crop < 0 || (crop & 1) || 2 * crop >= c->dc.N) return fail(c, GW_EINVAL, "crop must be even with 2 crop < N");
   if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
   s = enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out, params_f32, status, workspace, kStageParams,

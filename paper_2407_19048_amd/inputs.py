@@ -46,6 +46,12 @@ CONFIGS = {
 # reading; the paper only names the morphology)
 CONFIGS["sine_gaussian"] = dict(CONFIGS["paper_scale"], approximant=2, f0=(32.0, 1000.0), quality=(3.0, 30.0),
                                 hrss=(1e-23, 1e-21))
+# long-duration binary neutron stars: 256 s windows at 2048 Hz (N = 2^19),
+# TaylorF2, Welch over the preceding 64 s (ranges: a reading)
+CONFIGS["bns_long"] = dict(
+    det_ids=(0, 1, 2), fs=2048.0, t_window=256.0, psd_length=64.0, fftlen=2.0, overlap=1.0,
+    f_min=20.0, approximant=0, precision=1, mc=(1.0, 2.0), q=(0.5, 1.0), chi=(-0.05, 0.05),
+    dl=(20.0, 300.0), batch=256, log2_bg=27)
 CONFIGS["precision_study"] = dict(CONFIGS["paper_scale"], batch=8192)
 CONFIGS["surrogate"] = dict(CONFIGS["paper_scale"], batch=8192)
 

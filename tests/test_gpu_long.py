@@ -1,0 +1,104 @@
+"""Windows longer than 32768 samples (four-step transforms through HBM)
+against the oracle: the fused batch for every column length N2 = N/32768
+in {2, 4, 8, 16, 32}, and the inject and whiten steps (whitened relative L2
+per window <= 1e-5)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pipeline
+from paper_2407_19048_amd import gwgen, inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+_BG = {}
+
+
+def bg_for(fs, log2):
+    key = (fs, log2)
+    if key not in _BG:
+        _BG[key] = inputs.background(3, 1 << log2, fs, seed=1)
+    return _BG[key]
+
+
+@pytest.mark.parametrize("T", [32.0, 64.0, 128.0, 256.0, 512.0])
+def test_long_fused_batch_matches_oracle(T):
+    cfg = inputs.config("bns_long", t_window=T)
+    N = int(T * cfg["fs"])
+    bg_np = bg_for(2048.0, 22)
+    gen = gwgen.Generator(cfg)
+    B = 2
+    out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
+    st = torch.zeros(B, dtype=torch.int32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("long fused T=%g N=%d N2=%d" % (T, N, N // 32768))
+    gen.generate_batch(5, 1, B, torch.from_numpy(bg_np).to(DEV), out, ws, status=st)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        for d in range(3):
+            e = rel_l2(G[i, d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (T, i, d, e)
+    _say("long fused worst rel L2 %.3e" % worst)
+    assert (st.cpu().numpy() & ~gwgen.STATUS_CUT_AT_NYQUIST).max() == 0
+
+
+def test_long_inject_and_whiten_steps_match_oracle():
+    cfg = inputs.config("bns_long", t_window=128.0)
+    bg_np = bg_for(2048.0, 22)
+    gen = gwgen.Generator(cfg)
+    z = gen.sizes
+    B = 2
+    bg = torch.from_numpy(bg_np).to(DEV)
+    params = torch.empty((12, B), dtype=torch.float64, device=DEV)
+    offs = torch.empty(B, dtype=torch.int64, device=DEV)
+    gen.sample_params(7, 0, B, bg_np.shape[1], params, offs)
+    hp = torch.empty((B, z["F"]), dtype=torch.complex64, device=DEV)
+    hc = torch.empty_like(hp)
+    gen.gen_fd_waveform(params, hp, hc)
+    hdet = torch.empty((B, 3, z["F"]), dtype=torch.complex64, device=DEV)
+    gen.project_detectors(params, hp, hc, hdet)
+    strain = torch.empty((B, 3, z["N"]), dtype=torch.float32, device=DEV)
+    gen.inject(bg, offs, hdet, strain)
+    psd = torch.empty((B, 3, z["Fw"]), dtype=torch.float32, device=DEV)
+    gen.welch_psd(bg, offs, psd)
+    out = torch.empty_like(strain)
+    gen.whiten(strain, psd, out)
+    torch.cuda.synchronize()
+    P, O = params.cpu().numpy(), offs.cpu().numpy()
+    S, W = strain.cpu().numpy(), out.cpu().numpy()
+    for i in range(B):
+        ref, stg = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]), return_stages=True)
+        for d in range(3):
+            assert rel_l2(S[i, d], stg["y"][d]) <= 1e-6, (i, d)
+            assert rel_l2(W[i, d], ref[d]) <= 1e-5, (i, d)
+
+
+def test_long_windows_reject_unsupported_paths():
+    cfg = inputs.config("bns_long", t_window=64.0)
+    gen = gwgen.Generator(cfg)
+    with pytest.raises(gwgen.GWError):
+        gen.whiten_filter(torch.ones((3, gen.sizes["Fw"]), dtype=torch.float32, device=DEV), 64,
+                          torch.empty((3, gen.sizes["F"]), dtype=torch.float32, device=DEV))
