@@ -1,7 +1,7 @@
 """Learned waveform surrogate: ctypes wrapper of the gw_surrogate_* entry
 points and the training driver.
 
-The driver only sequences C-ABI calls: prior draws and plain-model targets
+The training loop only sequences C-ABI calls: prior draws and plain-model targets
 on the GPU, basis fit, skip-path fit, AdamW steps of the bfloat16 MFMA
 forward/backward kernels, and the fit of the mismatch head.  Weight
 initialisation draws seeded random numbers on the host and hands them over.
