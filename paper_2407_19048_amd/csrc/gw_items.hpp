@@ -125,22 +125,34 @@ constexpr int kSurrNodes = 1024;
 constexpr double kSurrLnMfLo = -6.2146080984221914;   // ln(2e-3)
 constexpr double kSurrDlog = 4.6051701859880914 / 1023.0;  // ln(0.2/2e-3)/(NN-1)
 
-// Whitening factor for window bin k in [0, N/2]; sets status bits.
+// Lower PSD bin for window bin k, clamped so that it and the next bin exist
+// for every k in [0, N/2] (the PSD has L/2 + 1 bins, L/2 = (N/2) / ratio).
+__device__ __forceinline__ int psd_index(const DevCfg& cf, int k, int NC) {
+  return min(k >> cf.log2_ratio, (NC >> cf.log2_ratio) - 1);
+}
+
+// Whitening factor for window bin k in [0, N/2] from the PSD values
+// s0 = psd[i], s1 = psd[i + 1], i = psd_index(k); sets status bits.
 template <class T>
-__device__ __forceinline__ T whiten_gain(const DevCfg& cf, const float* psd, int k, int NC, uint32_t& flag) {
+__device__ __forceinline__ T whiten_gain_at(const DevCfg& cf, float s0, float s1, int k, int NC, uint32_t& flag) {
   if (k == 0 || k >= NC || k < cf.kmin) return T(0);
   const int i = k >> cf.log2_ratio;
   const T tt = T(k - (i << cf.log2_ratio)) * T(cf.inv_ratio);
-  const T S = (T(1) - tt) * T(psd[i]) + tt * T(psd[i + 1]);
+  const T S = (T(1) - tt) * T(s0) + tt * T(s1);
   if (!isfinite(S)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
   if (!(S > T(0))) { flag |= GW_STATUS_NONPOSITIVE_PSD; return T(0); }
   return rsqrt_t(T(cf.fs) * S * T(0.5));
 }
 
-// Gain of a precomputed whitening filter at bin k; sets status bits.
 template <class T>
-__device__ __forceinline__ T filter_gain(const float* filt, int k, uint32_t& flag) {
-  const float g = filt[k];
+__device__ __forceinline__ T whiten_gain(const DevCfg& cf, const float* psd, int k, int NC, uint32_t& flag) {
+  const int i = psd_index(cf, k, NC);
+  return whiten_gain_at<T>(cf, psd[i], psd[i + 1], k, NC, flag);
+}
+
+// Gain g = filt[k] of a precomputed whitening filter; sets status bits.
+template <class T>
+__device__ __forceinline__ T filter_gain_at(float g, uint32_t& flag) {
   if (!isfinite(g)) { flag |= GW_STATUS_NONFINITE_PSD; return T(0); }
   return T(g);
 }
@@ -273,18 +285,52 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   }
   const float2* hsrc = reinterpret_cast<const float2*>(hrow);
 
+  // Global inputs of the pair (k, NC - k): the twiddle and what the two bins
+  // need (PSD values, filter gains, or the signal to inject), fetched one
+  // pair ahead so that their latency overlaps the previous pair's work.
+  struct PairIn {
+    cpx<T> W;
+    float g[4];
+  };
+  auto fetch = [&](int k) {
+    k = min(k, NC / 2);
+    const int km = NC - k;
+    PairIn q;
+    q.W = twr[k];  // exp(-2 pi i k / N)
+    if constexpr (SRC == 2) {
+      const float2 h0 = hsrc[k], h1 = hsrc[km];
+      q.g[0] = h0.x;
+      q.g[1] = h0.y;
+      q.g[2] = h1.x;
+      q.g[3] = h1.y;
+    } else if constexpr (SRC == 4) {
+      q.g[0] = psd[k];
+      q.g[1] = psd[km];
+      q.g[2] = q.g[3] = 0.f;
+    } else {
+      const int ia = psd_index(cf, k, NC), ib = psd_index(cf, km, NC);
+      q.g[0] = psd[ia];
+      q.g[1] = psd[ia + 1];
+      q.g[2] = psd[ib];
+      q.g[3] = psd[ib + 1];
+    }
+    return q;
+  };
+  PairIn nxt = fetch(t);
+
   // pairs (k, NC - k) for k in [0, NC/2]
 #pragma unroll 1
   for (int i = 0; i <= 8; ++i) {
     const int k = t + NT * i;
     if (k > NC / 2) break;
     const int km = NC - k;
-    const cpx<T> W = twr[k];  // exp(-2 pi i k / N)
+    const PairIn cur = nxt;
+    nxt = fetch(k + NT);
+    const cpx<T> W = cur.W;
     cpx<T> Yk, Ym;
     if constexpr (SRC == 2) {
-      const float2 h0 = hsrc[k], h1 = hsrc[km];
-      Yk = {T(h0.x), T(h0.y)};
-      Ym = {T(h1.x), T(h1.y)};
+      Yk = {T(cur.g[0]), T(cur.g[1])};
+      Ym = {T(cur.g[2]), T(cur.g[3])};
       if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
     } else {
       const int ia = lpad(k), ib = lpad(km & (NC - 1));
@@ -308,11 +354,11 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       }
       if constexpr (SRC == 4) {
         // fixed per-run filter row [NC + 1] (zero outside the kept band)
-        Yk = cscale(Xk, filter_gain<T>(psd, k, flag));
-        Ym = cscale(Xm, filter_gain<T>(psd, km, flag));
+        Yk = cscale(Xk, filter_gain_at<T>(cur.g[0], flag));
+        Ym = cscale(Xm, filter_gain_at<T>(cur.g[1], flag));
       } else {
-        Yk = cscale(Xk, whiten_gain<T>(cf, psd, k, NC, flag));
-        Ym = cscale(Xm, whiten_gain<T>(cf, psd, km, NC, flag));
+        Yk = cscale(Xk, whiten_gain_at<T>(cf, cur.g[0], cur.g[1], k, NC, flag));
+        Ym = cscale(Xm, whiten_gain_at<T>(cf, cur.g[2], cur.g[3], km, NC, flag));
       }
       if (km == k) Ym = Yk;
     }
