@@ -298,10 +298,11 @@ gw_status gw_set_tuning(gw_ctx* ctx, int32_t key, int64_t value);
 gw_status gw_get_tuning(const gw_ctx* ctx, int32_t key, int64_t* value);
 /* Autotuner: runs one batch of size B, then times the Welch kernel under
  * each (radix order, occupancy) and the fused window kernel under each radix
- * order, over `reps` launches each on a private stream (synchronous), and
- * keeps the fastest.  report (host double [6], nullable) receives the mean ms
- * of Welch (order 0, occ 2), (1, 2), (0, 3), (1, 3), then window order 0 and
- * 1.  Overwrites out and workspace. */
+ * order, over `reps` launches each on a private stream (synchronous), in
+ * three interleaved rounds, and keeps the fastest.  report (host double [6],
+ * nullable) receives, per variant, the best round's mean ms of Welch
+ * (order 0, occ 2), (1, 2), (0, 3), (1, 3), then window order 0 and 1.
+ * Overwrites out and workspace. */
 gw_status gw_autotune(gw_ctx* ctx, int64_t B, const float* bg, int64_t L_bg,
                       float* out, void* workspace, int64_t workspace_bytes,
                       int32_t reps, double* report);
@@ -372,10 +373,11 @@ gw_status gw_ragged_set_tuning(gw_ragged* r, int32_t key, int64_t value);
 gw_status gw_ragged_get_tuning(const gw_ragged* r, int32_t key, int64_t* value);
 /* Autotuner of the ragged stages (synchronous, private stream): times the
  * Welch stage over radix order x grid {1, 2, 4 per CU} and the window stage
- * over issue mode x radix order, `reps` launches each, and keeps the
- * fastest.  report (host double [10], nullable): mean ms of Welch (order 0,
- * grid 1, 2, 4), (order 1, grid 1, 2, 4), then window (mode 0, order 0),
- * (0, 1), (1, 0), (1, 1).  Overwrites out and workspace. */
+ * over issue mode x radix order, `reps` launches each, in three interleaved
+ * rounds, and keeps the fastest.  report (host double [10], nullable): the
+ * best round's mean ms of Welch (order 0, grid 1, 2, 4), (order 1, grid 1,
+ * 2, 4), then window (mode 0, order 0), (0, 1), (1, 0), (1, 1).  Overwrites
+ * out and workspace. */
 gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t* L_bg,
                              float* out, void* workspace, int64_t workspace_bytes,
                              int32_t reps, double* report);

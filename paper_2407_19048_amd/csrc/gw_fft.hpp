@@ -3,9 +3,8 @@
 //
 // Structure: Stockham auto-sort radix-R passes (radix 16 first, then 16s,
 // then one 2/4/8 pass when NC is not a power of 16).  Data is exchanged
-// between passes through LDS, in separate real/imaginary planes padded by one
-// word every 16 so that each pass's reads and writes are free of bank
-// conflicts.
+// between passes through LDS, in separate real/imaginary planes padded (see
+// pad_at) so that each pass's reads and writes are free of bank conflicts.
 //
 // Register layout of a thread t:
 //   before the first pass   v[r]     = x[t + NT*r]                (r < 16)
@@ -37,7 +36,26 @@ template <int DIR, class T> __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cp
   else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// LDS padding.  LDS has 32 banks of 4 bytes and serves a wavefront access to
+// binary32 words 32 lanes per cycle.  In a binary32 plane, index i is stored
+// at i + C (i >> 5): a run of 32 consecutive indices (every read of a pass,
+// every natural-order access) then covers 32 banks for any C, and C is chosen
+// per exchange for the stores of the pass that writes it (FftPad).  binary64
+// planes keep one pad element every 16.
+// pad_at(base, off) is the padded index of base + off for the index splits
+// used here, where (base mod 32) + (off mod 32) < 32, so that the padding of
+// base and of the compile-time offset off add up.
+template <class T, int C> __device__ __forceinline__ int pad_at(int base, int off) {
+  if constexpr (sizeof(T) == 4) {
+    return base + C * (base >> 5) + off + C * (off >> 5);
+  } else {
+    const int i = base + off;
+    return i + (i >> 4);
+  }
+}
+// natural-order layout (C = 1)
+template <class T> __device__ __forceinline__ int lpad(int i) { return pad_at<T, 1>(i, 0); }
+// padding never moves an index beyond NC + NC/16 (C <= 2 in every plan)
 template <int NC> struct LdsSize { static constexpr int value = NC + NC / 16; };
 
 // a * exp(DIR * 2 pi i m / 16), m a compile-time constant
@@ -158,6 +176,18 @@ template <int NC, int ORD> struct PlanEnds {
   static constexpr int RLAST = PassInfo<NC, FftPlan<NC>::NPASS - 1, ORD>::R;
 };
 
+// Padding constant of the exchange written by pass PASS.  Its stores form,
+// per run of 32 lanes, 32/NS groups of NS consecutive indices NS*R apart
+// (NS < 32) or one run of 32 consecutive indices (NS >= 32); C = 32/R puts
+// the groups on disjoint banks.  With NS = 1 the stores are R apart and C = 1
+// spreads them.
+template <int NC, int PASS, int ORD> struct FftPad {
+  static constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS;
+  static constexpr int C = (NS == 1 || NS >= 32) ? 1 : 32 / R;
+  static_assert(NS == 1 || NS >= 32 || NS * R >= 32, "groups must be 32 words apart");
+  static_assert(C <= 2, "padding must fit in LdsSize");
+};
+
 // Register slot of input x[t + NT*j] (j < 16) before the first pass.
 template <int NC, int ORD = 0> __host__ __device__ constexpr int fft_in_slot(int j) {
   constexpr int R0 = PlanEnds<NC, ORD>::RFIRST, NB = 16 / R0;
@@ -226,13 +256,16 @@ template <class T, int NC, int PASS, int DIR, bool READ, bool WRITE, int ORD, cl
 __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
   constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS;
   constexpr int NT = NC / 16, NB = 16 / R, STRIDE = NC / R;
+  // layout of the buffer read: written by the previous pass, or natural order
+  constexpr int CR = (PASS == 0) ? 1 : FftPad<NC, (PASS > 0 ? PASS - 1 : 0), ORD>::C;
+  constexpr int CW = FftPad<NC, PASS, ORD>::C;
   if constexpr (READ) {
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
       const int j = t + NT * m;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lpad(j + r * STRIDE);
+        const int i = pad_at<T, CR>(j, r * STRIDE);
         v[m * R + r] = {sre[i], sim[i]};
       }
     }
@@ -263,7 +296,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = lpad(base + r * NS);
+        const int i = pad_at<T, CW>(base, r * NS);
         sre[i] = v[m * R + r].x;
         sim[i] = v[m * R + r].y;
       }

@@ -30,6 +30,8 @@ struct gw_graph {
 };
 
 namespace gw {
+// Autotuners time every variant once per round and keep each one's best round.
+constexpr int kTuneRounds = 3;
 struct WinArgs;
 gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg);
 // Window stage of windows longer than 32768 samples (four-step transforms

@@ -254,7 +254,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int i = lpad(fft_out_index<NC, ORD>(t, e));
+      const int i = lpad<T>(fft_out_index<NC, ORD>(t, e));
       sre[i] = v[e].x;
       sim[i] = v[e].y;
     }
@@ -333,7 +333,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       Ym = {T(cur.g[2]), T(cur.g[3])};
       if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
     } else {
-      const int ia = lpad(k), ib = lpad(km & (NC - 1));
+      const int ia = lpad<T>(k), ib = lpad<T>(km & (NC - 1));
       const cpx<T> A = {sre[ia], sim[ia]};
       const cpx<T> Bm = {sre[ib], sim[ib]};
       const cpx<T> s = cadd(A, cconj(Bm));
@@ -365,11 +365,11 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
     const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
     const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
-    const int ia = lpad(k);
+    const int ia = lpad<T>(k);
     sre[ia] = p.x - q.y;
     sim[ia] = p.y + q.x;
     if (k != 0 && km != k) {
-      const int ib = lpad(km);
+      const int ib = lpad<T>(km);
       sre[ib] = p.x + q.y;
       sim[ib] = -p.y + q.x;
     }
@@ -431,9 +431,11 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
   constexpr int NT = NC / 16;
   constexpr int LS = LdsSize<NC>::value;
   static_assert(NC * sizeof(ACC) <= 2 * LS * sizeof(T), "fold buffer must fit in the FFT buffer");
-  T w[16];
+  // periodic Hann window sin^2(pi n / L) at n = t + NT r, r < 8; half a
+  // segment later it is cos^2 = 1 - sin^2, applied as x - w x
+  T w[8];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < 8; ++r) {
     const T sp = sinpi_t(T(t + NT * r) / T(NC));
     w[r] = sp * sp;
   }
@@ -460,7 +462,7 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), w[r] * T(na[r])};
-      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), w[r + 8] * T(nb[r])};
+      v[fft_in_slot<NC, ORD>(r + 8)] = {T(na[r]) - w[r] * T(na[r]), T(nb[r]) - w[r] * T(nb[r])};
       cur[r] = nb[r];
     }
     const float* xn = x + int64_t(p + 1) * NC;
@@ -485,7 +487,7 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), T(0)};
-      v[fft_in_slot<NC, ORD>(r + 8)] = {w[r + 8] * T(na[r]), T(0)};
+      v[fft_in_slot<NC, ORD>(r + 8)] = {T(na[r]) - w[r] * T(na[r]), T(0)};
     }
     if (nfull > 0) __syncthreads();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);

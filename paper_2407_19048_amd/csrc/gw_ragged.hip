@@ -725,7 +725,8 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const int saved[5] = {r->ord_welch, r->grid_welch, r->ord_win, r->grid_win, r->win_mode};
   const int grids[3] = {1, 2, 4};
-  double ms[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[10];
+  std::fill(ms, ms + 10, 1e300);  // best of kTuneRounds interleaved rounds
   auto time_stage = [&](int stage, double* res) {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, stage, st);  // warm-up
     (void)hipEventRecord(e0, st);
@@ -735,25 +736,27 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
     if (hipEventSynchronize(e1) != hipSuccess && s == GW_OK) s = rfail(r, GW_EHIP, "hipEventSynchronize");
     float t = 0.f;
     (void)hipEventElapsedTime(&t, e0, e1);
-    *res = double(t) / reps;
+    *res = std::min(*res, double(t) / reps);
   };
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     s = rfail(r, GW_EHIP, "hipEventCreate");
   } else {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, kStageAll, st);
-    for (int o = 0; o < 2 && s == GW_OK; ++o)
-      for (int gi = 0; gi < 3 && s == GW_OK; ++gi) {
-        r->ord_welch = o;
-        r->grid_welch = grids[gi];
-        time_stage(kStageWelch, &ms[o * 3 + gi]);
-      }
-    for (int m = 0; m < 2 && s == GW_OK; ++m)
-      for (int o = 0; o < 2 && s == GW_OK; ++o) {
-        r->ord_win = o;
-        r->win_mode = m;
-        r->grid_win = saved[3];
-        time_stage(kStageWindow, &ms[6 + 2 * m + o]);
-      }
+    for (int round = 0; round < kTuneRounds && s == GW_OK; ++round) {
+      for (int o = 0; o < 2 && s == GW_OK; ++o)
+        for (int gi = 0; gi < 3 && s == GW_OK; ++gi) {
+          r->ord_welch = o;
+          r->grid_welch = grids[gi];
+          time_stage(kStageWelch, &ms[o * 3 + gi]);
+        }
+      for (int m = 0; m < 2 && s == GW_OK; ++m)
+        for (int o = 0; o < 2 && s == GW_OK; ++o) {
+          r->ord_win = o;
+          r->win_mode = m;
+          r->grid_win = saved[3];
+          time_stage(kStageWindow, &ms[6 + 2 * m + o]);
+        }
+    }
   }
   if (s == GW_OK) {
     int best = 0;

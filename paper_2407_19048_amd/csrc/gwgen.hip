@@ -266,11 +266,11 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
     const cpx<T> Ym = km == k ? Yk : cpx<T>{whiten_gain<T>(cf, psd, km, NC, flag), T(0)};
     const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
     const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
-    sre[lpad(k)] = p.x - q.y;
-    sim[lpad(k)] = p.y + q.x;
+    sre[lpad<T>(k)] = p.x - q.y;
+    sim[lpad<T>(k)] = p.y + q.x;
     if (k != 0 && km != k) {
-      sre[lpad(km)] = p.x + q.y;
-      sim[lpad(km)] = -p.y + q.x;
+      sre[lpad<T>(km)] = p.x + q.y;
+      sim[lpad<T>(km)] = -p.y + q.x;
     }
   }
   __syncthreads();
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const int i = lpad(fft_out_index<NC, 0>(t, e));
+    const int i = lpad<T>(fft_out_index<NC, 0>(t, e));
     sre[i] = v[e].x;
     sim[i] = v[e].y;
   }
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
   // 3. forward real transform of the tapered response
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int i = lpad(t + NT * j);
+    const int i = lpad<T>(t + NT * j);
     v[fft_in_slot<NC, 0>(j)] = {sre[i], sim[i]};
   }
   __syncthreads();
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const int i = lpad(fft_out_index<NC, 0>(t, e));
+    const int i = lpad<T>(fft_out_index<NC, 0>(t, e));
     sre[i] = v[e].x;
     sim[i] = v[e].y;
   }
@@ -323,8 +323,8 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
     if (k > NC / 2) break;
     const int km = NC - k;
     const cpx<T> W = twr[k];
-    const cpx<T> A = {sre[lpad(k)], sim[lpad(k)]};
-    const cpx<T> Bm = {sre[lpad(km & (NC - 1))], sim[lpad(km & (NC - 1))]};
+    const cpx<T> A = {sre[lpad<T>(k)], sim[lpad<T>(k)]};
+    const cpx<T> Bm = {sre[lpad<T>(km & (NC - 1))], sim[lpad<T>(km & (NC - 1))]};
     const cpx<T> s = cadd(A, cconj(Bm));
     const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
     out[k] = float(fabs(T(0.5) * (s.x + u.y)));
@@ -1089,7 +1089,10 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(c, GW_EHIP, "hipStreamCreate");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // Welch variants: (order, occupancy) = (0,2), (1,2), (0,3), (1,3); window: order 0, 1
-  double ms[6] = {0, 0, 0, 0, 0, 0};
+  // best of kTuneRounds interleaved rounds, so that clock ramps and other
+  // drifts do not favour the variants timed last
+  double ms[6];
+  std::fill(ms, ms + 6, 1e300);
   const bool b64 = c->dc.precision == 2;
   const int saved[3] = {c->dc.ord_welch, c->dc.occ_welch, c->dc.ord_win};
   auto time_stage = [&](int mask, double* res) {
@@ -1101,22 +1104,24 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
     if (hipEventSynchronize(e1) != hipSuccess && s == GW_OK) s = fail(c, GW_EHIP, "hipEventSynchronize");
     float t = 0.f;
     (void)hipEventElapsedTime(&t, e0, e1);
-    *res = double(t) / reps;
+    *res = std::min(*res, double(t) / reps);
   };
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     s = fail(c, GW_EHIP, "hipEventCreate");
   } else {
     s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, kStageAll, st);
-    for (int v = 0; v < 4 && s == GW_OK; ++v) {
-      if (b64 && v > 0) { ms[v] = ms[0]; continue; }
-      c->dc.ord_welch = v & 1;
-      c->dc.occ_welch = 2 + (v >> 1);
-      time_stage(kStageWelch, &ms[v]);
-    }
-    for (int o = 0; o < 2 && s == GW_OK; ++o) {
-      if (b64 && o > 0) { ms[4 + o] = ms[4]; continue; }
-      c->dc.ord_win = o;
-      time_stage(kStageWindow, &ms[4 + o]);
+    for (int round = 0; round < kTuneRounds && s == GW_OK; ++round) {
+      for (int v = 0; v < 4 && s == GW_OK; ++v) {
+        if (b64 && v > 0) { ms[v] = ms[0]; continue; }
+        c->dc.ord_welch = v & 1;
+        c->dc.occ_welch = 2 + (v >> 1);
+        time_stage(kStageWelch, &ms[v]);
+      }
+      for (int o = 0; o < 2 && s == GW_OK; ++o) {
+        if (b64 && o > 0) { ms[4 + o] = ms[4]; continue; }
+        c->dc.ord_win = o;
+        time_stage(kStageWindow, &ms[4 + o]);
+      }
     }
   }
   if (s == GW_OK) {
