@@ -398,6 +398,9 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   }
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Twiddles of passes 1.. kept in registers for the whole segment loop.
 template <class T, int NC, int ORD> struct RegTwiddle {
   cpx<T> p[FftPlan<NC>::NPASS][16];
@@ -425,6 +428,9 @@ template <class T, int NC, int ORD> struct RegTwiddle {
 // at stride L/2.  Segments 2p and 2p+1 go through ONE complex FFT as real and
 // imaginary parts; since |A_k|^2 + |B_k|^2 = (|X_k|^2 + |X_{L-k}|^2)/2 for
 // X = FFT(a + i b), the accumulated |X|^2 is folded once at the end.
+// |X|^2 is summed in T in two levels: runs of kWelchRun transforms, then the
+// run sums, so that the rounding error grows with kWelchRun + K/(2 kWelchRun)
+// rather than with K; the fold and the normalisation are done in ACC.
 template <class T, class ACC, int NC, int ORD>
 __device__ __forceinline__ void welch_item(int K, double norm, int t, const float* x, float* out, const cpx<T>* twtab,
                                            T* sre, T* sim, bool active) {
@@ -441,9 +447,10 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
   }
   RegTwiddle<T, NC, ORD> tw;
   tw.init(twtab, t);
-  ACC acc[16];
+  constexpr int kWelchRun = 16;
+  T run[16], tot[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = ACC(0);
+  for (int e = 0; e < 16; ++e) run[e] = tot[e] = T(0);
   // Pair p covers [p L, p L + 3L/2).  Its first half-segment was read by
   // pair p-1; the next pair's 16 new values per thread are requested before
   // the current transform so that their latency hides behind it.
@@ -479,7 +486,14 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
     if (p > 0) __syncthreads();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
+    for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
+    if (p % kWelchRun == kWelchRun - 1) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        tot[e] += run[e];
+        run[e] = T(0);
+      }
+    }
   }
   if (nfull < npairs) {
     // the last segment alone: real input, zero imaginary part
@@ -492,12 +506,12 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
     if (nfull > 0) __syncthreads();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] += ACC(v[e].x * v[e].x + v[e].y * v[e].y);
+    for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
   }
   __syncthreads();
   ACC* fold = reinterpret_cast<ACC*>(sre);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = acc[e];
+  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = ACC(tot[e] + run[e]);
   __syncthreads();
   if (active) {
     for (int k = t; k <= NC / 2; k += NT) {
