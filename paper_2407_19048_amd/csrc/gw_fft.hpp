@@ -36,6 +36,12 @@ template <int DIR, class T> __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cp
   else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
+// Workgroup barrier for the LDS exchanges: waits only for this wave's LDS
+// operations (lgkmcnt) before s_barrier.  __syncthreads() also waits for
+// every outstanding global load, which would expose the latency of loads
+// issued ahead of time (next segment, next pass's twiddles) at each pass.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // LDS padding.  LDS has 32 banks of 4 bytes and serves a wavefront access to
 // binary32 words 32 lanes per cycle.  In a binary32 plane, index i is stored
 // at i + C (i >> 5): a run of 32 consecutive indices (every read of a pass,
@@ -214,25 +220,43 @@ template <class T, int NC, int ORD = 0> struct TableTwiddle {
 // the table and the other powers are products of at most three of them
 // (rounding error a few ulp).  Used where twiddle loads would otherwise
 // dominate the load count and register pressure.
+// block_fft requests each pass's table values during the pass before it
+// (Base, load), so that their latency is hidden behind that pass.
 template <class T, int NC, int ORD = 0> struct PowTwiddle {
   const cpx<T>* __restrict__ tw;
-  template <int PASS, int R> __device__ __forceinline__ void all(int k, cpx<T>* w) const {
-    constexpr int NS = PassInfo<NC, PASS, ORD>::NS;
-    constexpr int STEP = NC / (NS * R);
-    const int i1 = k * STEP;
-    w[1] = tw[i1];
+  // table values of one pass: per butterfly m, W^(2^l) for l < NL
+  template <int PASS> struct Base {
+    static constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS, NB = 16 / R;
+    static constexpr int NL = (NS == 1) ? 0 : (R >= 16) ? 4 : (R >= 8) ? 3 : (R >= 4) ? 2 : 1;
+    cpx<T> b[NB][NL > 0 ? NL : 1];
+  };
+  template <int PASS> __device__ __forceinline__ Base<PASS> load(int t) const {
+    using B = Base<PASS>;
+    constexpr int NT = NC / 16, STEP = NC / (B::NS * B::R);
+    B q;
+#pragma unroll
+    for (int m = 0; m < B::NB; ++m) {
+      const int i1 = ((t + NT * m) & (B::NS - 1)) * STEP;
+#pragma unroll
+      for (int l = 0; l < B::NL; ++l) q.b[m][l] = tw[(1 << l) * i1];
+    }
+    return q;
+  }
+  // powers W^1 .. W^(R-1) from W, W^2, W^4, W^8
+  template <int R> __device__ static __forceinline__ void expand(const cpx<T>* b, cpx<T>* w) {
+    w[1] = b[0];
     if constexpr (R >= 4) {
-      w[2] = tw[2 * i1];
+      w[2] = b[1];
       w[3] = cmul(w[2], w[1]);
     }
     if constexpr (R >= 8) {
-      w[4] = tw[4 * i1];
+      w[4] = b[2];
       w[5] = cmul(w[4], w[1]);
       w[6] = cmul(w[4], w[2]);
       w[7] = cmul(w[6], w[1]);
     }
     if constexpr (R >= 16) {
-      w[8] = tw[8 * i1];
+      w[8] = b[3];
       w[9] = cmul(w[8], w[1]);
       w[10] = cmul(w[8], w[2]);
       w[11] = cmul(w[10], w[1]);
@@ -251,9 +275,10 @@ template <class T, int NC, int ORD> struct TwiddleIsPow<PowTwiddle<T, NC, ORD>> 
 // it).  WRITE: scatter the output to LDS (else it stays in registers in the
 // final layout).  A barrier separates this pass's LDS reads from its writes;
 // the caller must ensure the LDS buffer is free before a pass that WRITEs
-// without READing.
+// without READing.  pre: the pass's PowTwiddle table values, already loaded.
 template <class T, int NC, int PASS, int DIR, bool READ, bool WRITE, int ORD, class TW>
-__device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
+__device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const TW& tw,
+                                         const cpx<T>* pre = nullptr) {
   constexpr int R = PassInfo<NC, PASS, ORD>::R, NS = PassInfo<NC, PASS, ORD>::NS;
   constexpr int NT = NC / 16, NB = 16 / R, STRIDE = NC / R;
   // layout of the buffer read: written by the previous pass, or natural order
@@ -277,7 +302,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
       const int k = j & (NS - 1);
       if constexpr (TwiddleIsPow<TW>::value) {
         cpx<T> w[R];
-        tw.template all<PASS, R>(k, w);
+        TW::template expand<R>(pre + m * TW::template Base<PASS>::NL, w);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[m * R + r] = twmul<DIR>(v[m * R + r], w[r]);
       } else {
@@ -288,7 +313,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
     dftR<R, DIR>(v + m * R);
   }
   if constexpr (WRITE) {
-    if constexpr (READ) __syncthreads();
+    if constexpr (READ) lds_barrier();
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
       const int j = t + NT * m;
@@ -301,7 +326,7 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
         sim[i] = v[m * R + r].y;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -312,14 +337,29 @@ __device__ __forceinline__ void fft_pass(cpx<T>* v, T* sre, T* sim, int t, const
 template <class T, int NC, int DIR, bool FIRST_FROM_LDS, int ORD = 0, class TW>
 __device__ __forceinline__ void block_fft(cpx<T>* v, T* sre, T* sim, int t, const TW& tw) {
   using P = FftPlan<NC>;
-  fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true, ORD>(v, sre, sim, t, tw);
-  if constexpr (P::NPASS == 3) {
-    fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 2, DIR, true, false, ORD>(v, sre, sim, t, tw);
+  if constexpr (TwiddleIsPow<TW>::value) {
+    // each pass's table values are requested before the pass ahead of it
+    const auto b1 = tw.template load<1>(t);
+    fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true, ORD>(v, sre, sim, t, tw);
+    const auto b2 = tw.template load<2>(t);
+    fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw, &b1.b[0][0]);
+    if constexpr (P::NPASS == 3) {
+      fft_pass<T, NC, 2, DIR, true, false, ORD>(v, sre, sim, t, tw, &b2.b[0][0]);
+    } else {
+      const auto b3 = tw.template load<3>(t);
+      fft_pass<T, NC, 2, DIR, true, true, ORD>(v, sre, sim, t, tw, &b2.b[0][0]);
+      fft_pass<T, NC, 3, DIR, true, false, ORD>(v, sre, sim, t, tw, &b3.b[0][0]);
+    }
   } else {
-    fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 2, DIR, true, true, ORD>(v, sre, sim, t, tw);
-    fft_pass<T, NC, 3, DIR, true, false, ORD>(v, sre, sim, t, tw);
+    fft_pass<T, NC, 0, DIR, FIRST_FROM_LDS, true, ORD>(v, sre, sim, t, tw);
+    if constexpr (P::NPASS == 3) {
+      fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
+      fft_pass<T, NC, 2, DIR, true, false, ORD>(v, sre, sim, t, tw);
+    } else {
+      fft_pass<T, NC, 1, DIR, true, true, ORD>(v, sre, sim, t, tw);
+      fft_pass<T, NC, 2, DIR, true, true, ORD>(v, sre, sim, t, tw);
+      fft_pass<T, NC, 3, DIR, true, false, ORD>(v, sre, sim, t, tw);
+    }
   }
 }
 

@@ -251,14 +251,14 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       v[fft_in_slot<NC, ORD>(j)] = {T(q.x), T(q.y)};
     }
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int i = lpad<T>(fft_out_index<NC, ORD>(t, e));
       sre[i] = v[e].x;
       sim[i] = v[e].y;
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   T cpl = T(0), cxx = T(0);
@@ -374,7 +374,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       sim[ib] = -p.y + q.x;
     }
   }
-  __syncthreads();
+  lds_barrier();
   block_fft<T, NC, +1, true, ORD>(v, sre, sim, t, tw);
   const T sc = T(1) / T(NC);
   if (active) {
@@ -483,7 +483,7 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
 #pragma unroll
       for (int r = 0; r < 8; ++r) na[r] = xn[t + NT * (r + 8)];
     }
-    if (p > 0) __syncthreads();
+    if (p > 0) lds_barrier();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
 #pragma unroll
     for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
@@ -503,16 +503,16 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
       v[fft_in_slot<NC, ORD>(r)] = {w[r] * T(cur[r]), T(0)};
       v[fft_in_slot<NC, ORD>(r + 8)] = {T(na[r]) - w[r] * T(na[r]), T(0)};
     }
-    if (nfull > 0) __syncthreads();
+    if (nfull > 0) lds_barrier();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
 #pragma unroll
     for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
   }
-  __syncthreads();
+  lds_barrier();
   ACC* fold = reinterpret_cast<ACC*>(sre);
 #pragma unroll
   for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = ACC(tot[e] + run[e]);
-  __syncthreads();
+  lds_barrier();
   if (active) {
     for (int k = t; k <= NC / 2; k += NT) {
       const ACC s = (fold[k] + fold[(NC - k) & (NC - 1)]) * ACC(0.5);
