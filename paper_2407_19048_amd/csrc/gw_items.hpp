@@ -174,6 +174,21 @@ __device__ __forceinline__ cpx<T> burst_bin(const DevCfg& cf, const WfScalars& w
           A * (gp * (cxx * cp - cpl * sp) - gm * (cpl * sm + cxx * cm))};
 }
 
+// Same, with k^(1/3) and ln(k)/3 given by the caller (kc, lk).
+template <class T, class TP, bool FULL>
+__device__ __forceinline__ cpx<T> signal_bin_at(const DevCfg& cf, const WfScalars& w, T cpl, T cxx, double tauT,
+                                                int k, double kc, double lk) {
+  if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
+  if (cf.approximant == 2) return burst_bin<T, TP>(cf, w, cpl, cxx, tauT, k);
+  TP rev = wf_phase_rev<TP, FULL>(w, k, kc, lk, cf.invT) + TP(w.pconst) + TP(k) * TP(tauT);
+  rev = frac1(rev);
+  T s, c;
+  sincos_rev(T(rev), &s, &c);
+  const T A = T(cf.fs) * wf_amplitude<T>(w, k, kc, cf.invT);
+  // fs A (cpl - i cxx)(c - i s)
+  return {A * (cpl * c - cxx * s), -A * (cpl * s + cxx * c)};
+}
+
 template <class T, class TP, bool FULL>
 __device__ __forceinline__ cpx<T> signal_bin(const DevCfg& cf, const WinArgs& a, const WfScalars& w, T cpl, T cxx,
                                              double tauT, int k) {

@@ -68,6 +68,10 @@ struct LongArgs {
   const void* tw1;     // cpx<float>[N1]: exp(-2 pi i n / N1)
   const float* x;      // real input of the forward columns (strain rows or the background)
   int NC, N2, l2n2;    // NC = N1 N2, l2n2 = log2(N2)
+  // bin tables in the transposed layout (bin k at (k mod N2) N1 + k / N2):
+  const double* kc_t;        // k^(1/3)
+  const double* lk_t;        // ln(k)/3
+  const cpx<float>* twr_t;   // exp(-2 pi i k / N)
 };
 
 // x row of window item bd (SRC 0: strain [B][D][N]; SRC 1, 2: background at o + P)
@@ -153,26 +157,45 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rows(LongArgs a) {
   for (int e = 0; e < 16; ++e) row[fft_out_index<kN1, 0>(t, e)] = {v[e].x, v[e].y};
 }
 
-// Bins: one thread per pair (k, NC - k), k in [0, NC/2]; grid
-// (ceil((NC/2 + 1)/256), B*D).  SRC 0 whitens, SRC 1 adds the in-register
-// signal and whitens, SRC 2 packs the given projected spectrum (inject).
+// Bins: one thread per pair (k, NC - k), k in [0, NC/2].  SRC 0 whitens,
+// SRC 1 adds the in-register signal and whitens, SRC 2 packs the given
+// projected spectrum (inject).
+// SRC 0, 1: grid (N1/256, B*D, N2/2 + 1); thread (k1, r) takes the element
+// at row r, column k1 of X'[k2][k1] = X[k2 + N2 k1], i.e. k = r + N2 k1, or
+// its mirror NC - k (row N2 - r, column N1 - 1 - k1) when k > NC/2, so that
+// a wavefront reads and writes runs of consecutive (or reversed) columns of
+// two rows, and reads the bin tables in the same transposed layout.  Rows 0
+// and N2/2 pair with themselves and use half their columns.
+// SRC 2 reads hdet by k: grid (ceil((NC/2 + 1)/256), B*D, 1), k = thread.
 template <class TP, int SRC>
 __global__ __launch_bounds__(256) void k_long_bins(LongArgs a, const float* hdet) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
   const int64_t bd = blockIdx.y;
   const DevCfg& cf = a.w.cf;
   const int NC = a.NC, N2 = a.N2;
+  int k;
+  bool valid;
+  if constexpr (SRC == 2) {
+    k = blockIdx.x * 256 + threadIdx.x;
+    valid = k <= NC / 2;
+  } else {
+    const int k1 = blockIdx.x * 256 + threadIdx.x;  // < N1
+    const int r = blockIdx.z;
+    const int kr = r + N2 * k1;
+    valid = (r == 0) ? (k1 <= kN1 / 2) : (2 * r == N2) ? (k1 < kN1 / 2) : true;
+    k = min(kr, NC - kr);
+  }
   __shared__ uint32_t sflag;
   if (threadIdx.x == 0) sflag = 0u;
   __syncthreads();
-  if (k <= NC / 2) {
+  if (valid) {
     const int64_t b = bd / cf.n_det;
     const int d = int(bd - b * cf.n_det);
     float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
     const int km = NC - k;
     // X[kk] sits at X'[kk mod N2][kk / N2]
     auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
-    const cpx<float> W = reinterpret_cast<const cpx<float>*>(a.twr)[k];  // exp(-2 pi i k / N)
+    // exp(-2 pi i k / N)
+    const cpx<float> W = (SRC == 2) ? reinterpret_cast<const cpx<float>*>(a.twr)[k] : a.twr_t[pos(k)];
     uint32_t flag = 0;
     cpx<float> Yk, Ym;
     if constexpr (SRC == 2) {
@@ -193,8 +216,10 @@ __global__ __launch_bounds__(256) void k_long_bins(LongArgs a, const float* hdet
         const float cpl = float(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
         const float cxx = float(dsh.fx * wsh.cosi);
         const double tauT = dsh.tau * cf.invT;
-        Xk = cadd(Xk, signal_bin<float, TP, false>(cf, a.w, wsh, cpl, cxx, tauT, k));
-        if (km != k) Xm = cadd(Xm, signal_bin<float, TP, false>(cf, a.w, wsh, cpl, cxx, tauT, km));
+        const int64_t pk = pos(k), pm = pos(km);
+        const double kck = a.kc_t[pk], lkk = a.lk_t[pk], kcm = a.kc_t[pm], lkm = a.lk_t[pm];
+        Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, k, kck, lkk));
+        if (km != k) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, kcm, lkm));
       }
       const float* psd = a.w.psd + bd * cf.Fw;
       Yk = cscale(Xk, whiten_gain<float>(cf, psd, k, NC, flag));
@@ -255,12 +280,18 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   a.N2 = a.NC / kN1;
   a.l2n2 = 0;
   while ((1 << a.l2n2) < a.N2) ++a.l2n2;
+  const char* tabs = static_cast<const char*>(c->long_tabs);
+  a.kc_t = reinterpret_cast<const double*>(tabs);
+  a.lk_t = reinterpret_cast<const double*>(tabs + sizeof(double) * size_t(a.NC));
+  a.twr_t = reinterpret_cast<const cpx<float>*>(tabs + 2 * sizeof(double) * size_t(a.NC));
   if (items <= 0) return GW_OK;
   if (items > 65535) return ctx_fail(c, GW_EINVAL, "long windows: at most 65535 (sample, detector) items per call");
-  const dim3 bins_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
+  if (!c->long_tabs) return ctx_fail(c, GW_EUNSUPPORTED, "long windows need the binary32 tables");
+  const dim3 bins_grid(unsigned(kN1 / 256), unsigned(items), unsigned(a.N2 / 2 + 1));
+  const dim3 inject_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
   const dim3 rows_grid(unsigned(items * a.N2));
   if (src == 2) {
-    hipLaunchKernelGGL((k_long_bins<double, 2>), bins_grid, dim3(256), 0, st, a, hdet);
+    hipLaunchKernelGGL((k_long_bins<double, 2>), inject_grid, dim3(256), 0, st, a, hdet);
     hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
     launch_cols_inv<2>(a, items, st);
     return ctx_check_launch(c, "long inject");

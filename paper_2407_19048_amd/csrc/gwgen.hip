@@ -462,6 +462,30 @@ gw_status upload_twiddles(gw_ctx* c, void** dst, int n, int denom) {
   return GW_OK;
 }
 
+// Per-bin tables of the long-window bins pass in the transposed layout of
+// its spectrum (row k mod N2, column k / N2, rows of 16384): one allocation
+// of double[NC] k^(1/3), double[NC] ln(k)/3, cpx<float>[NC] exp(-2 pi i k/N).
+gw_status upload_long_tables(gw_ctx* c, int NC) {
+  const int N1 = 16384, N2 = NC / N1;
+  std::vector<double> kc(NC), lk(NC);
+  std::vector<cpx<float>> tw(NC);
+  for (int k = 0; k < NC; ++k) {
+    const int p = (k % N2) * N1 + k / N2;
+    kc[p] = std::cbrt(double(k));
+    lk[p] = k > 0 ? std::log(double(k)) / 3.0 : 0.0;
+    const double ang = -2.0 * M_PI * double(k) / double(2 * NC);
+    tw[p] = {float(std::cos(ang)), float(std::sin(ang))};
+  }
+  const size_t nd = sizeof(double) * size_t(NC), nt = sizeof(cpx<float>) * size_t(NC);
+  if (hipMalloc(&c->long_tabs, 2 * nd + nt) != hipSuccess) return fail(c, GW_ENOMEM, "hipMalloc long tables");
+  char* base = static_cast<char*>(c->long_tabs);
+  if (hipMemcpy(base, kc.data(), nd, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + nd, lk.data(), nd, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + 2 * nd, tw.data(), nt, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, GW_EHIP, "hipMemcpy long tables");
+  return GW_OK;
+}
+
 gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   auto bad = [&](const char* m) { *why = m; return GW_EINVAL; };
   if (!g) return bad("config is NULL");
@@ -750,6 +774,7 @@ gw_status gw_destroy(gw_ctx* c) {
   (void)hipFree(c->twr_win);
   (void)hipFree(c->tw_welch);
   (void)hipFree(c->tw_long);
+  (void)hipFree(c->long_tabs);
   delete c;
   return GW_OK;
 }
@@ -794,6 +819,7 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->tw_welch, dc.L, dc.L);
     if (s == GW_OK && NC > 16384) s = upload_twiddles<float>(c, &c->tw_long, NC, NC);
+    if (s == GW_OK && NC > 16384) s = upload_long_tables(c, NC);
   }
   if (s != GW_OK) {
     gw_destroy(c);
