@@ -178,6 +178,7 @@ def long_leg(bg, args, K, W, dev):
     B = cfg["batch"]
     out = torch.empty((B, z["D"], z["N"]), dtype=torch.float32, device=dev)
     ws = gen.alloc_workspace(B, device=dev)
+    gen.autotune(B, bg, out, ws, reps=2)
     graph = gen.graph(2, 0, B, bg, out, ws)
     for _ in range(W):
         graph.launch()
