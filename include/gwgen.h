@@ -289,7 +289,8 @@ gw_status gw_graph_destroy(gw_graph* graph);
 /* Kernel variants.  GW_TUNE_ORD_*: 0 puts the FFT's small radix pass last,
  * 1 puts it first (same result up to rounding; which is faster depends on
  * the size).  GW_TUNE_OCC_WELCH: 2 or 3 waves per SIMD for the Welch kernel
- * (3 trades spilled twiddles for occupancy).  Binary64 kernels (precision 2)
+ * (3 caps it at 168 VGPRs, which the binary32 kernels meet without spills
+ * at L = 4096).  Binary64 kernels (precision 2)
  * have one variant. */
 #define GW_TUNE_ORD_WINDOW 1
 #define GW_TUNE_ORD_WELCH  2

@@ -13,8 +13,8 @@
 // Workgroups pull group indices from an atomic counter until the queue is
 // empty.  Groups are ordered largest transform first, so the tail of the
 // launch is made of the shortest items.  The two stages are separate
-// launches because the Welch item keeps ~210 VGPRs of twiddles and
-// accumulators live (two waves per SIMD), while a 1024-thread window
+// launches because the persistent Welch kernel keeps ~240 VGPRs of twiddles
+// and accumulators live (two waves per SIMD), while a 1024-thread window
 // workgroup is limited to 128 VGPRs.
 #include <hip/hip_runtime.h>
 
