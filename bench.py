@@ -391,7 +391,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this generator has no cross-GPU step "
-              "(samples are independent), and multi-GPU runs are not part of this build",
+              "(samples are independent), so a run on N GPUs is N independent copies of this one",
               file=sys.stderr)
         sys.exit(2)
 

@@ -49,7 +49,7 @@ typedef int32_t gw_status;
 #define GW_EINVAL       -1  /* bad argument or configuration               */
 #define GW_ENOMEM       -2  /* device allocation failed (gw_create only)    */
 #define GW_EHIP         -3  /* a HIP call or kernel launch failed           */
-#define GW_EUNSUPPORTED -4  /* valid, but not supported by this build       */
+#define GW_EUNSUPPORTED -4  /* valid, but not supported by this library     */
 
 /* Per-sample status bits (uint32), OR-ed over the sample's detectors. */
 #define GW_STATUS_NONFINITE_PSD  1u  /* a PSD bin was NaN/Inf (bad background) */

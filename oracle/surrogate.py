@@ -3,7 +3,7 @@ physics features of the linear skip path, the MLP forward and backward pass
 with bfloat16 rounding at the same points as the GPU, waveform
 reconstruction and the noise-weighted mismatch.
 
-The paper does not use a surrogate; it is an addition of this build to the
+The paper does not use a surrogate; it is an addition of this library to the
 waveform step of section 3.1 (one of the workload's three system choices).
 Readings:
 
