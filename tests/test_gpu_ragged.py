@@ -312,6 +312,43 @@ def test_autotuners_keep_results():
     check_slots(classes, cls, 4, 0, bgs_np, r, list(range(0, 24, 3)))
 
 
+def test_launch_shape_invariance():
+    """Launch shapes that only change how the same items are spread over
+    workgroups give bitwise-identical results: the plain Welch kernel at 2 and
+    3 waves per SIMD, and the persistent ragged launches at every grid.  A
+    missing LDS barrier or a queue race would show up as a difference."""
+    cfg = inputs.config("paper_scale")
+    bg = _gpu(bg_for(2048.0, 19))
+    B = 16
+    outs = []
+    for occ in (2, 3):
+        gen = gwgen.Generator(cfg)
+        gen.set_tuning(gwgen.TUNE_OCC_WELCH, occ)
+        gen.set_tuning(gwgen.TUNE_ORD_WINDOW, 1)
+        out = torch.empty((B, 3, gen.sizes["N"]), dtype=torch.float32, device=DEV)
+        ws = gen.alloc_workspace(B)
+        _say("plain batch, Welch at %d waves per SIMD" % occ)
+        gen.generate_batch(3, 1, B, bg, out, ws)
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+    classes = inputs.ragged_classes()
+    bgs_np = class_bgs(classes, 19)
+    cls = _balanced(30, seed=8)
+    ref = None
+    for gw, gv in ((1, 1), (2, 1), (4, 2)):
+        _say("ragged batch, Welch grid %d, window grid %d" % (gw, gv))
+        r = run_ragged(classes, cls, 5, 2, bgs_np,
+                       tune={gwgen.RTUNE_GRID_WELCH: gw, gwgen.RTUNE_GRID_WINDOW: gv, gwgen.RTUNE_WINDOW_MODE: 0,
+                             gwgen.RTUNE_ORD_WELCH: 0, gwgen.RTUNE_ORD_WINDOW: 1})
+        if ref is None:
+            ref = r
+        else:
+            assert np.array_equal(r["psd"], ref["psd"])
+            assert np.array_equal(r["out"], ref["out"])
+
+
 def test_ragged_rejects_bad_input():
     classes = inputs.ragged_classes()
     with pytest.raises(gwgen.GWError):
