@@ -84,7 +84,8 @@ typedef struct gw_config {
   int32_t approximant;         /* 0 TaylorF2 3.5PN, 1 IMR-form, 2 sine-Gaussian
                                   burst (rows 0-2 of params are f0, Q, hrss) */
   int32_t precision;           /* 0 binary32 throughout, 1 mixed (binary64
-                                  waveform phase and time shift), 2 binary64 */
+                                  waveform phase, time shift and Welch
+                                  sums), 2 binary64 */
   double  mc[2], q[2], chi[2], dl[2];   /* prior ranges [Msun], [], [], [Mpc] */
   double  f0[2], quality[2], hrss[2];   /* approximant 2 only: central
                                   frequency [Hz] (uniform, below fs/2),

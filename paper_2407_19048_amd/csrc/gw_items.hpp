@@ -443,9 +443,11 @@ template <class T, int NC, int ORD> struct RegTwiddle {
 // at stride L/2.  Segments 2p and 2p+1 go through ONE complex FFT as real and
 // imaginary parts; since |A_k|^2 + |B_k|^2 = (|X_k|^2 + |X_{L-k}|^2)/2 for
 // X = FFT(a + i b), the accumulated |X|^2 is folded once at the end.
-// |X|^2 is summed in T in two levels: runs of kWelchRun transforms, then the
-// run sums, so that the rounding error grows with kWelchRun + K/(2 kWelchRun)
-// rather than with K; the fold and the normalisation are done in ACC.
+// With ACC wider than T (mixed precision) every transform's |X|^2 is added
+// to ACC totals.  With ACC equal to T it is summed in two levels, runs of
+// kWelchRun transforms and then the run sums, so that the rounding error
+// grows with kWelchRun + K/(2 kWelchRun) terms rather than K/2.  The fold and
+// the normalisation are done in ACC.
 template <class T, class ACC, int NC, int ORD>
 __device__ __forceinline__ void welch_item(int K, double norm, int t, const float* x, float* out, const cpx<T>* twtab,
                                            T* sre, T* sim, bool active) {
@@ -462,10 +464,32 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
   }
   RegTwiddle<T, NC, ORD> tw;
   tw.init(twtab, t);
+  constexpr bool kWide = sizeof(ACC) > sizeof(T);
   constexpr int kWelchRun = 16;
-  T run[16], tot[16];
+  ACC tot[16];
+  T run[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) run[e] = tot[e] = T(0);
+  for (int e = 0; e < 16; ++e) {
+    tot[e] = ACC(0);
+    run[e] = T(0);
+  }
+  // |X|^2 of transform p (p < 0: the last, single-segment transform)
+  auto add_power = [&](const cpx<T>* v, int p) {
+    if constexpr (kWide) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) tot[e] += ACC(fma_t(v[e].y, v[e].y, v[e].x * v[e].x));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
+      if (p % kWelchRun == kWelchRun - 1) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          tot[e] += run[e];
+          run[e] = T(0);
+        }
+      }
+    }
+  };
   // Pair p covers [p L, p L + 3L/2).  Its first half-segment was read by
   // pair p-1; the next pair's 16 new values per thread are requested before
   // the current transform so that their latency hides behind it.
@@ -500,15 +524,7 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
     }
     if (p > 0) lds_barrier();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
-    if (p % kWelchRun == kWelchRun - 1) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        tot[e] += run[e];
-        run[e] = T(0);
-      }
-    }
+    add_power(v, p);
   }
   if (nfull < npairs) {
     // the last segment alone: real input, zero imaginary part
@@ -520,13 +536,12 @@ __device__ __forceinline__ void welch_item(int K, double norm, int t, const floa
     }
     if (nfull > 0) lds_barrier();
     block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) run[e] = fma_t(v[e].y, v[e].y, fma_t(v[e].x, v[e].x, run[e]));
+    add_power(v, -1);
   }
   lds_barrier();
   ACC* fold = reinterpret_cast<ACC*>(sre);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = ACC(tot[e] + run[e]);
+  for (int e = 0; e < 16; ++e) fold[fft_out_index<NC, ORD>(t, e)] = tot[e] + ACC(run[e]);
   lds_barrier();
   if (active) {
     for (int k = t; k <= NC / 2; k += NT) {

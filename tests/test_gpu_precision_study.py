@@ -1,6 +1,6 @@
 """Precision study at the paper-scale shape with batch 8192: binary32
-throughout (mode 0) vs binary64 waveform phase and time shift (mode 1,
-default) vs binary64 throughout (mode 2).  Per-stage relative L2 and phase
+throughout (mode 0) vs binary64 waveform phase, time shift and Welch sums
+(mode 1, default) vs binary64 throughout (mode 2).  Per-stage relative L2 and phase
 error against the FP64 oracle on 24 samples spread over the batch."""
 
 import math
