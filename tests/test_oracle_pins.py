@@ -461,6 +461,21 @@ def test_welch_matches_scipy():
         np.testing.assert_allclose(mine, ref, rtol=1e-12, atol=0)
 
 
+def test_welch_parseval():
+    """Parseval for the one-sided density: summed over bins times df = fs/L,
+    each segment's estimate is the mean square of the windowed segment divided
+    by the window's mean square, for any input.  Pins the factor 2 on the
+    interior bins, the fs and the window normalisation together."""
+    rs = np.random.default_rng(7)
+    for (L, S, K, fs) in ((64, 32, 1, 128.0), (4096, 2048, 5, 2048.0), (2048, 1024, 3, 1024.0)):
+        x = rs.standard_normal((K - 1) * S + L) * 2.5 + np.cos(np.arange((K - 1) * S + L) * 0.11)
+        psd = spectral.welch_psd(x, fs, L, S)
+        w = 0.5 * (1 - np.cos(2 * np.pi * np.arange(L) / L))
+        want = np.mean([np.sum((w * x[s * S:s * S + L]) ** 2) / np.sum(w * w) for s in range(K)])
+        got = np.sum(psd) * fs / L
+        assert abs(got / want - 1) < 1e-12
+
+
 def test_welch_brute_force_dft():
     rs = np.random.default_rng(2)
     P, L, S, fs = 160, 32, 16, 64.0
