@@ -556,7 +556,11 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   while (k > 0 && double(k - 1) / g->t_window >= g->f_min) --k;
   while (double(k) / g->t_window < g->f_min) ++k;
   c.kmin = k;
-  c.occ_welch = 2;
+  // defaults before any autotuning: the variants measured fastest at the
+  // paper-scale shape (binary32 transforms of L = 4096 fit 3 waves per SIMD
+  // without spills; the 8192-point window prefers its radix-2 pass first)
+  c.occ_welch = (c.L == 4096 && c.precision != 2) ? 3 : 2;
+  c.ord_win = (c.N == 16384 && c.precision != 2) ? 1 : 0;
   for (int d = 0; d < g->n_det; ++d) c.det[d] = make_detector(g->det_id[d]);
   *dc = c;
   return GW_OK;
