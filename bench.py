@@ -336,7 +336,8 @@ def ragged_leg(bg2048, args, K, W, dev):
     tuned = {"ord_window": rg.get_tuning(gwgen.RTUNE_ORD_WINDOW), "ord_welch": rg.get_tuning(gwgen.RTUNE_ORD_WELCH),
              "grid_window": rg.get_tuning(gwgen.RTUNE_GRID_WINDOW),
              "grid_welch": rg.get_tuning(gwgen.RTUNE_GRID_WELCH),
-             "window_mode": rg.get_tuning(gwgen.RTUNE_WINDOW_MODE)}
+             "window_mode": rg.get_tuning(gwgen.RTUNE_WINDOW_MODE),
+             "welch_mode": rg.get_tuning(gwgen.RTUNE_WELCH_MODE)}
     log("ragged autotune %s -> %s" % (table, tuned))
     graph = rg.graph(2, 0, bgs, out, ws, params_f32=pf, status=st)
     for _ in range(W):
@@ -363,7 +364,7 @@ def ragged_leg(bg2048, args, K, W, dev):
         nbytes += int(n) * 3 * (P + 2 * N) * 4
     ms = 1e3 * el / K
     gbs = nbytes / (el / K) / 1e9
-    welch_best = min(table["welch"].values())
+    welch_best = min(list(table["welch"].values()) + list(table["welch_class"].values()))
     win_best = min(table["window"].values())
     log("ragged: %.3f ms/batch, %.0f samples/s, %.0f GB/s algorithmic" % (ms, Br / (el / K), gbs))
     return {
@@ -374,7 +375,8 @@ def ragged_leg(bg2048, args, K, W, dev):
         "bytes_per_step": nbytes, "class_counts": np.bincount(cls, minlength=len(classes)).tolist(),
         "stage_ms": {"welch": round(welch_best, 4), "window": round(win_best, 4)},
         "autotune_ms": {"welch_ord%d_grid%d" % k: round(v, 4) for k, v in table["welch"].items()}
-        | {"window_mode%d_ord%d" % k: round(v, 4) for k, v in table["window"].items()},
+        | {"window_mode%d_ord%d" % k: round(v, 4) for k, v in table["window"].items()}
+        | {"welch_per_class_ord%d" % k: round(v, 4) for k, v in table["welch_class"].items()},
         "tuned": tuned,
     }
 

@@ -365,23 +365,28 @@ gw_status gw_ragged_graph_create(gw_ragged* r, uint64_t seed, uint64_t first_bat
                                  gw_graph** graph);
 /* Ragged kernel variants: radix orders as for gw_set_tuning, the
  * persistent grid of each stage in workgroups per compute unit (1..8), and
- * the window stage's issue mode: 0 one persistent launch over all classes
- * (default), 1 one launch per class (largest first) with one NC/16-thread
- * workgroup per item. */
+ * each stage's issue mode.  Window mode: 0 one persistent launch over all
+ * classes (default), 1 one launch per class (largest first) with one
+ * NC/16-thread workgroup per item.  Welch mode: 0 one persistent launch, 1
+ * one launch per class (largest transform first, default) with one
+ * L/16-thread workgroup per item at 3 waves per SIMD; the Welch grid only
+ * applies to mode 0. */
 #define GW_RTUNE_ORD_WINDOW 1
 #define GW_RTUNE_ORD_WELCH  2
 #define GW_RTUNE_GRID_WINDOW 3
 #define GW_RTUNE_GRID_WELCH  4
 #define GW_RTUNE_WINDOW_MODE 5
+#define GW_RTUNE_WELCH_MODE  6
 gw_status gw_ragged_set_tuning(gw_ragged* r, int32_t key, int64_t value);
 gw_status gw_ragged_get_tuning(const gw_ragged* r, int32_t key, int64_t* value);
 /* Autotuner of the ragged stages (synchronous, private stream): times the
- * Welch stage over radix order x grid {1, 2, 4 per CU} and the window stage
- * over issue mode x radix order, `reps` launches each, in three interleaved
- * rounds, and keeps the fastest.  report (host double [10], nullable): the
- * best round's mean ms of Welch (order 0, grid 1, 2, 4), (order 1, grid 1,
- * 2, 4), then window (mode 0, order 0), (0, 1), (1, 0), (1, 1).  Overwrites
- * out and workspace. */
+ * Welch stage over radix order x grid {1, 2, 4 per CU} in mode 0 and radix
+ * order in mode 1, and the window stage over issue mode x radix order,
+ * `reps` launches each, in three interleaved rounds, and keeps the fastest.
+ * report (host double [12], nullable): the best round's mean ms of Welch
+ * mode 0 (order 0, grid 1, 2, 4), (order 1, grid 1, 2, 4), then window
+ * (mode 0, order 0), (0, 1), (1, 0), (1, 1), then Welch mode 1 (order 0),
+ * (order 1).  Overwrites out and workspace. */
 gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t* L_bg,
                              float* out, void* workspace, int64_t workspace_bytes,
                              int32_t reps, double* report);

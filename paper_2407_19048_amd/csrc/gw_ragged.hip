@@ -64,6 +64,8 @@ struct gw_ragged {
   int ord_win = 0, ord_welch = 0, grid_win = 1, grid_welch = 2;
   int win_mode = 0;                      // 0: one persistent launch, 1: one launch per class
   int cls_first[kMaxCls], cls_items[kMaxCls];  // window item range of each class
+  int wcls_first[kMaxCls], wcls_items[kMaxCls];  // Welch item range of each class
+  int welch_mode = 1;  // Welch issue: 0 one persistent launch, 1 one launch per class
   std::string err;
 };
 
@@ -153,6 +155,22 @@ __device__ __forceinline__ int welch_size_loop(const RWelchArgs& a, int g, int e
     g = __builtin_amdgcn_readfirstlane(*s_g);
   }
   return g;
+}
+
+// One class per launch: block i takes the class's i-th Welch item, L/16
+// threads, 3 waves per SIMD (no queue loop, so only one item's state is live).
+template <class ACC, int L, int ORD>
+__global__ __launch_bounds__(L / 16, 3) void k_welch_class(RWelchArgs a, int cls, int first) {
+  constexpr int LS = LdsSize<L>::value;
+  __shared__ float lds[2 * LS];
+  const int it = load_const(a.items + first + int(blockIdx.x));
+  const DevCfg cf = load_const(a.cfgs + cls);
+  const int D = cf.n_det;
+  const int b = it / D, d = it - b * D;
+  const float* x = a.bg[cls] + int64_t(d) * a.L_bg[cls] + load_const(a.offset + b);
+  float* out = a.psd + load_const(a.psd_off + b) + int64_t(d) * cf.Fw;
+  const cpx<float>* tw = reinterpret_cast<const cpx<float>*>(L == 4096 ? a.tw4096 : a.tw2048);
+  welch_item<float, ACC, L, ORD>(cf.K, a.norm[cls], threadIdx.x, x, out, tw, lds, lds + LS, true);
 }
 
 template <class ACC, int ORD>
@@ -355,6 +373,22 @@ constexpr int kStageParams = 1, kStageWelch = 2, kStageWindow = 4, kStageAll = 7
 
 template <class ACC>
 void launch_welch_ragged(const gw_ragged* r, const RWelchArgs& a, hipStream_t st) {
+  if (r->welch_mode == 1) {
+    // largest transforms first
+    for (int pass = 0; pass < 2; ++pass)
+      for (int c = 0; c < r->n_cls; ++c) {
+        const int L = r->dc[c].L;
+        if (r->wcls_items[c] == 0 || (pass == 0) != (L == 4096)) continue;
+        const dim3 grid(unsigned(r->wcls_items[c]));
+        if (L == 4096)
+          hipLaunchKernelGGL((k_welch_class<ACC, 4096, 0>), grid, dim3(256), 0, st, a, c, r->wcls_first[c]);
+        else if (r->ord_welch)
+          hipLaunchKernelGGL((k_welch_class<ACC, 2048, 1>), grid, dim3(128), 0, st, a, c, r->wcls_first[c]);
+        else
+          hipLaunchKernelGGL((k_welch_class<ACC, 2048, 0>), grid, dim3(128), 0, st, a, c, r->wcls_first[c]);
+      }
+    return;
+  }
   const dim3 grid = dim3(unsigned(r->n_cu * r->grid_welch));
   if (r->ord_welch) hipLaunchKernelGGL((k_welch_ragged<ACC, 1>), grid, dim3(kWelchThreads), 0, st, a);
   else hipLaunchKernelGGL((k_welch_ragged<ACC, 0>), grid, dim3(kWelchThreads), 0, st, a);
@@ -569,10 +603,14 @@ gw_status gw_ragged_create(const gw_config* classes, int32_t n_classes, const in
   std::vector<int32_t> wi, vi;
   build(true, wg, wi);
   build(false, vg, vi);
-  for (int c = 0; c < kMaxCls; ++c) r->cls_first[c] = r->cls_items[c] = 0;
+  for (int c = 0; c < kMaxCls; ++c) r->cls_first[c] = r->cls_items[c] = r->wcls_first[c] = r->wcls_items[c] = 0;
   for (const int4& g : vg) {
     if (r->cls_items[g.x] == 0) r->cls_first[g.x] = g.y;
     r->cls_items[g.x] += g.z;
+  }
+  for (const int4& g : wg) {
+    if (r->wcls_items[g.x] == 0) r->wcls_first[g.x] = g.y;
+    r->wcls_items[g.x] += g.z;
   }
   r->n_wgroups = int(wg.size());
   r->n_vgroups = int(vg.size());
@@ -696,6 +734,10 @@ gw_status gw_ragged_set_tuning(gw_ragged* r, int32_t key, int64_t value) {
       if (value < 0 || value > 1) return rfail(r, GW_EINVAL, "window mode must be 0 or 1");
       r->win_mode = int(value);
       return GW_OK;
+    case GW_RTUNE_WELCH_MODE:
+      if (value < 0 || value > 1) return rfail(r, GW_EINVAL, "Welch mode must be 0 or 1");
+      r->welch_mode = int(value);
+      return GW_OK;
     default: return rfail(r, GW_EINVAL, "unknown tuning key");
   }
 }
@@ -708,6 +750,7 @@ gw_status gw_ragged_get_tuning(const gw_ragged* r, int32_t key, int64_t* value) 
     case GW_RTUNE_GRID_WINDOW: *value = r->grid_win; break;
     case GW_RTUNE_GRID_WELCH: *value = r->grid_welch; break;
     case GW_RTUNE_WINDOW_MODE: *value = r->win_mode; break;
+    case GW_RTUNE_WELCH_MODE: *value = r->welch_mode; break;
     default: return GW_EINVAL;
   }
   return GW_OK;
@@ -723,10 +766,10 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return rfail(r, GW_EHIP, "hipStreamCreate");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const int saved[5] = {r->ord_welch, r->grid_welch, r->ord_win, r->grid_win, r->win_mode};
+  const int saved[6] = {r->ord_welch, r->grid_welch, r->ord_win, r->grid_win, r->win_mode, r->welch_mode};
   const int grids[3] = {1, 2, 4};
-  double ms[10];
-  std::fill(ms, ms + 10, 1e300);  // best of kTuneRounds interleaved rounds
+  double ms[12];
+  std::fill(ms, ms + 12, 1e300);  // best of kTuneRounds interleaved rounds
   auto time_stage = [&](int stage, double* res) {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, stage, st);  // warm-up
     (void)hipEventRecord(e0, st);
@@ -743,12 +786,18 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
   } else {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, kStageAll, st);
     for (int round = 0; round < kTuneRounds && s == GW_OK; ++round) {
+      r->welch_mode = 0;
       for (int o = 0; o < 2 && s == GW_OK; ++o)
         for (int gi = 0; gi < 3 && s == GW_OK; ++gi) {
           r->ord_welch = o;
           r->grid_welch = grids[gi];
           time_stage(kStageWelch, &ms[o * 3 + gi]);
         }
+      r->welch_mode = 1;
+      for (int o = 0; o < 2 && s == GW_OK; ++o) {
+        r->ord_welch = o;
+        time_stage(kStageWelch, &ms[10 + o]);
+      }
       for (int m = 0; m < 2 && s == GW_OK; ++m)
         for (int o = 0; o < 2 && s == GW_OK; ++o) {
           r->ord_win = o;
@@ -762,20 +811,29 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
     int best = 0;
     for (int k = 1; k < 6; ++k)
       if (ms[k] < ms[best]) best = k;
-    r->ord_welch = best / 3;
-    r->grid_welch = grids[best % 3];
+    const int bc = ms[11] < ms[10] ? 11 : 10;
+    if (ms[bc] < ms[best]) {
+      r->welch_mode = 1;
+      r->ord_welch = bc - 10;
+      r->grid_welch = saved[1];
+    } else {
+      r->welch_mode = 0;
+      r->ord_welch = best / 3;
+      r->grid_welch = grids[best % 3];
+    }
     int bw = 6;
     for (int k = 7; k < 10; ++k)
       if (ms[k] < ms[bw]) bw = k;
     r->win_mode = (bw - 6) / 2;
     r->ord_win = (bw - 6) % 2;
-    if (report) std::copy(ms, ms + 10, report);
+    if (report) std::copy(ms, ms + 12, report);
   } else {
     r->ord_welch = saved[0];
     r->grid_welch = saved[1];
     r->ord_win = saved[2];
     r->grid_win = saved[3];
     r->win_mode = saved[4];
+    r->welch_mode = saved[5];
   }
   (void)hipStreamSynchronize(st);
   if (e0) (void)hipEventDestroy(e0);

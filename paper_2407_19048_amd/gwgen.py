@@ -43,6 +43,7 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
 
 TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH, RTUNE_WINDOW_MODE = 1, 2, 3, 4, 5
+RTUNE_WELCH_MODE = 6
 (RQ_B, RQ_OUT_FLOATS, RQ_PSD_FLOATS, RQ_WORKSPACE, RQ_PSD_OFFSET, RQ_NCLASSES) = range(6)
 RAGGED_MAX_CLASSES = 8
 
@@ -591,16 +592,17 @@ class Ragged:
         return v.value
 
     def autotune(self, bgs, out, workspace, reps=3):
-        """Pick radix orders and the Welch grid; returns the timing table [ms]."""
+        """Pick radix orders, the Welch issue mode and grid; returns the timing table [ms]."""
         nbytes = self._common(out, workspace, None, None)
         ptrs, lens = self._bg_arrays(bgs)
-        rep = (ctypes.c_double * 10)()
+        rep = (ctypes.c_double * 12)()
         self._check(lib().gw_ragged_autotune(self._h, ctypes.cast(ptrs, ctypes.c_void_p),
                                              ctypes.cast(lens, ctypes.c_void_p), _ptr(out), _ptr(workspace),
                                              nbytes, int(reps), ctypes.cast(rep, ctypes.c_void_p)),
                     "gw_ragged_autotune")
         return {"welch": {(o, g): rep[o * 3 + i] for o in (0, 1) for i, g in enumerate((1, 2, 4))},
-                "window": {(m, o): rep[6 + 2 * m + o] for m in (0, 1) for o in (0, 1)}}
+                "window": {(m, o): rep[6 + 2 * m + o] for m in (0, 1) for o in (0, 1)},
+                "welch_class": {o: rep[10 + o] for o in (0, 1)}}
 
     def signal(self, out, i):
         """View [D][N_i] of signal slot i in the flat output."""

@@ -304,9 +304,10 @@ def test_autotuners_keep_results():
     table = rg.autotune(bgs, rout, rws, reps=2)
     _say("ragged autotune: %s" % table)
     assert all(v > 0 for v in table["welch"].values()) and all(v > 0 for v in table["window"].values())
+    assert all(v > 0 for v in table["welch_class"].values())
     tuned = {k: rg.get_tuning(k) for k in (gwgen.RTUNE_ORD_WINDOW, gwgen.RTUNE_ORD_WELCH,
                                           gwgen.RTUNE_GRID_WINDOW, gwgen.RTUNE_GRID_WELCH,
-                                          gwgen.RTUNE_WINDOW_MODE)}
+                                          gwgen.RTUNE_WINDOW_MODE, gwgen.RTUNE_WELCH_MODE)}
     _say("ragged tuned: %s" % tuned)
     r = run_ragged(classes, cls, 4, 0, bgs_np, tune=tuned)
     check_slots(classes, cls, 4, 0, bgs_np, r, list(range(0, 24, 3)))
@@ -315,8 +316,9 @@ def test_autotuners_keep_results():
 def test_launch_shape_invariance():
     """Launch shapes that only change how the same items are spread over
     workgroups give bitwise-identical results: the plain Welch kernel at 2 and
-    3 waves per SIMD, and the persistent ragged launches at every grid.  A
-    missing LDS barrier or a queue race would show up as a difference."""
+    3 waves per SIMD, the persistent ragged launches at every grid, and the
+    per-class Welch launch.  A missing LDS barrier or a queue race would show
+    up as a difference."""
     cfg = inputs.config("paper_scale")
     bg = _gpu(bg_for(2048.0, 19))
     B = 16
@@ -337,11 +339,11 @@ def test_launch_shape_invariance():
     bgs_np = class_bgs(classes, 19)
     cls = _balanced(30, seed=8)
     ref = None
-    for gw, gv in ((1, 1), (2, 1), (4, 2)):
-        _say("ragged batch, Welch grid %d, window grid %d" % (gw, gv))
+    for wm, gw, gv in ((0, 1, 1), (0, 2, 1), (0, 4, 2), (1, 1, 1)):
+        _say("ragged batch, Welch mode %d grid %d, window grid %d" % (wm, gw, gv))
         r = run_ragged(classes, cls, 5, 2, bgs_np,
-                       tune={gwgen.RTUNE_GRID_WELCH: gw, gwgen.RTUNE_GRID_WINDOW: gv, gwgen.RTUNE_WINDOW_MODE: 0,
-                             gwgen.RTUNE_ORD_WELCH: 0, gwgen.RTUNE_ORD_WINDOW: 1})
+                       tune={gwgen.RTUNE_WELCH_MODE: wm, gwgen.RTUNE_GRID_WELCH: gw, gwgen.RTUNE_GRID_WINDOW: gv,
+                             gwgen.RTUNE_WINDOW_MODE: 0, gwgen.RTUNE_ORD_WELCH: 0, gwgen.RTUNE_ORD_WINDOW: 1})
         if ref is None:
             ref = r
         else:
