@@ -17,7 +17,7 @@ struct gw_ctx {
   void* tw_win = nullptr;     // cpx<T>[N/2]
   void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
   void* tw_welch = nullptr;   // cpx<T>[L]
-  void* tw_long = nullptr;    // cpx<float>[N/2] for windows longer than 32768 samples
+  void* tw_long = nullptr;    // cpx<float>[N2][16384]: W_NC^(m1 k2), windows longer than 32768 samples
   // windows longer than 32768 samples: k^(1/3), ln(k)/3 (double[N/2] each) and
   // exp(-2 pi i k / N) (cpx<float>[N/2]) for k < N/2, stored at the position
   // (k mod N2) N1 + k / N2 of bin k in the transposed four-step spectrum

@@ -63,7 +63,7 @@ __device__ __forceinline__ void dft_small(cpx<T>* a) {
 
 struct LongArgs {
   WinArgs w;           // cf, tables, per-sample data, psd, status; out = the in-place buffer
-  const void* twn;     // cpx<float>[NC]: exp(-2 pi i n / NC)
+  const void* twc;     // cpx<float>[N2][N1]: exp(-2 pi i m1 k2 / NC) at [k2][m1]
   const void* twr;     // cpx<float>[NC/2 + 1]: exp(-2 pi i k / N)
   const void* tw1;     // cpx<float>[N1]: exp(-2 pi i n / N1)
   const float* x;      // real input of the forward columns (strain rows or the background)
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_long_cols_fwd(LongArgs a) {
   const int64_t bd = blockIdx.y;
   const float* x = long_input<SRC>(a, bd);
   float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * a.NC;
-  const cpx<float>* twn = reinterpret_cast<const cpx<float>*>(a.twn);
+  const cpx<float>* twc = reinterpret_cast<const cpx<float>*>(a.twc);
   cpx<float> v[N2];
 #pragma unroll
   for (int m2 = 0; m2 < N2; ++m2) {
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_long_cols_fwd(LongArgs a) {
   dft_small<N2, -1>(v);
 #pragma unroll
   for (int k2 = 0; k2 < N2; ++k2) {
-    const cpx<float> w = k2 ? cmul(v[k2], twn[(m1 * k2) & (a.NC - 1)]) : v[k2];
+    const cpx<float> w = k2 ? cmul(v[k2], twc[k2 * kN1 + m1]) : v[k2];
     buf[int64_t(k2) * kN1 + m1] = {w.x, w.y};
   }
 }
@@ -114,13 +114,13 @@ __global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
   const int m1 = blockIdx.x * 256 + threadIdx.x;
   const int64_t bd = blockIdx.y;
   float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * a.NC;
-  const cpx<float>* twn = reinterpret_cast<const cpx<float>*>(a.twn);
+  const cpx<float>* twc = reinterpret_cast<const cpx<float>*>(a.twc);
   cpx<float> v[N2];
 #pragma unroll
   for (int k2 = 0; k2 < N2; ++k2) {
     const float2 q = buf[int64_t(k2) * kN1 + m1];
     const cpx<float> u = {q.x, q.y};
-    v[k2] = k2 ? twmul<+1>(u, twn[(m1 * k2) & (a.NC - 1)]) : u;
+    v[k2] = k2 ? twmul<+1>(u, twc[k2 * kN1 + m1]) : u;
   }
   dft_small<N2, +1>(v);
   const float sc = 1.f / float(a.NC);
@@ -272,7 +272,7 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   const DevCfg& d = c->dc;
   LongArgs a;
   a.w = w;
-  a.twn = c->tw_long;
+  a.twc = c->tw_long;
   a.twr = c->twr_win;
   a.tw1 = c->tw_win;
   a.x = x;

@@ -465,10 +465,12 @@ gw_status upload_twiddles(gw_ctx* c, void** dst, int n, int denom) {
 // Per-bin tables of the long-window bins pass in the transposed layout of
 // its spectrum (row k mod N2, column k / N2, rows of 16384): one allocation
 // of double[NC] k^(1/3), double[NC] ln(k)/3, cpx<float>[NC] exp(-2 pi i k/N).
+// Also the column twiddles W_NC^(m1 k2) at [k2][m1] (c->tw_long), so that a
+// wavefront's threads (consecutive m1) read consecutive entries.
 gw_status upload_long_tables(gw_ctx* c, int NC) {
   const int N1 = 16384, N2 = NC / N1;
   std::vector<double> kc(NC), lk(NC);
-  std::vector<cpx<float>> tw(NC);
+  std::vector<cpx<float>> tw(NC), twc(NC);
   for (int k = 0; k < NC; ++k) {
     const int p = (k % N2) * N1 + k / N2;
     kc[p] = std::cbrt(double(k));
@@ -476,6 +478,16 @@ gw_status upload_long_tables(gw_ctx* c, int NC) {
     const double ang = -2.0 * M_PI * double(k) / double(2 * NC);
     tw[p] = {float(std::cos(ang)), float(std::sin(ang))};
   }
+  for (int k2 = 0; k2 < N2; ++k2)
+    for (int m1 = 0; m1 < N1; ++m1) {
+      const int n = int((int64_t(m1) * k2) & (NC - 1));
+      const double ang = -2.0 * M_PI * double(n) / double(NC);
+      twc[size_t(k2) * N1 + m1] = {float(std::cos(ang)), float(std::sin(ang))};
+    }
+  if (hipMalloc(&c->tw_long, sizeof(cpx<float>) * size_t(NC)) != hipSuccess)
+    return fail(c, GW_ENOMEM, "hipMalloc column twiddles");
+  if (hipMemcpy(c->tw_long, twc.data(), sizeof(cpx<float>) * size_t(NC), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, GW_EHIP, "hipMemcpy column twiddles");
   const size_t nd = sizeof(double) * size_t(NC), nt = sizeof(cpx<float>) * size_t(NC);
   if (hipMalloc(&c->long_tabs, 2 * nd + nt) != hipSuccess) return fail(c, GW_ENOMEM, "hipMalloc long tables");
   char* base = static_cast<char*>(c->long_tabs);
@@ -822,7 +834,6 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
     s = upload_twiddles<float>(c, &c->tw_win, NCt, NCt);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->tw_welch, dc.L, dc.L);
-    if (s == GW_OK && NC > 16384) s = upload_twiddles<float>(c, &c->tw_long, NC, NC);
     if (s == GW_OK && NC > 16384) s = upload_long_tables(c, NC);
   }
   if (s != GW_OK) {
