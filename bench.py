@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "whitened 3-det 8s@2048Hz samples/sec (plain vs surrogate) + % HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# binary32 vector peak without packed instructions (none are generated in this
-# build): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# binary32 vector peak without packed instructions (the library is compiled
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_PEAK_PACKED_TFLOPS = 157.3
 
