@@ -47,7 +47,7 @@ extern "C" {
 typedef int32_t gw_status;
 #define GW_OK            0
 #define GW_EINVAL       -1  /* bad argument or configuration               */
-#define GW_ENOMEM       -2  /* device allocation failed (gw_create only)    */
+#define GW_ENOMEM       -2  /* device allocation failed (allocating calls)  */
 #define GW_EHIP         -3  /* a HIP call or kernel launch failed           */
 #define GW_EUNSUPPORTED -4  /* valid, but not supported by this library     */
 
@@ -70,8 +70,13 @@ typedef int32_t gw_status;
  * stretch preceding the window.  L = fftlen*fs is the Welch segment length and
  * S = (fftlen - overlap)*fs is the segment stride.  K = (P - L)/S + 1
  * segments are averaged.  Constraints: N and L are powers of two,
- * 2^11 <= N <= 2^15, 2^11 <= L <= 2^12, N/L is an integer, and
- * (P - L) is a multiple of S.  The stride must be L/2 (50 % overlap). */
+ * 2^11 <= N <= 2^20, 2^11 <= L <= 2^12, N/L is an integer, and
+ * (P - L) is a multiple of S.  The stride must be L/2 (50 % overlap).
+ * Precision mode 2 allows N up to 2^14 (gw_create returns GW_EUNSUPPORTED
+ * above).  Windows longer than 2^15 samples run as a four-step transform
+ * inside the output buffer, through the six steps and gw_generate_batch; the
+ * surrogate, per-run-PSD, view-pair and ragged calls return GW_EUNSUPPORTED
+ * for them. */
 typedef struct gw_config {
   int32_t n_det;               /* 1..4 */
   int32_t det_id[GW_MAX_DET];  /* 0 = H1, 1 = L1, 2 = V1 */
@@ -98,7 +103,10 @@ typedef struct gw_surrogate gw_surrogate;
 
 /* Create a context: validate the configuration, build detector geometry and
  * twiddle/power tables on the current HIP device.  Allocates device memory
- * (about 0.5 MB); this is the only entry point that allocates. */
+ * for them (under 1 MB up to N = 2^15, about 32 MB at N = 2^20).  The only
+ * other calls that allocate are gw_ragged_create, gw_surrogate_create and
+ * gw_surrogate_fit_basis (a temporary Gram buffer); gw_graph_create and
+ * gw_ragged_graph_create instantiate HIP graphs. */
 gw_status gw_create(const gw_config* cfg, gw_ctx** out);
 gw_status gw_destroy(gw_ctx* ctx);
 const char* gw_strerror(gw_status s);
