@@ -1,6 +1,7 @@
 """Windows longer than 32768 samples (four-step transforms through HBM)
 against the oracle: the fused batch for every column length N2 = N/32768
-in {2, 4, 8, 16, 32}, and the inject and whiten steps (whitened relative L2
+in {2, 4, 8, 16, 32}, the benchmark's batch of 256 at N = 2^19 (sampled),
+sine-Gaussian bursts, and the inject and whiten steps (whitened relative L2
 per window <= 1e-5)."""
 
 import sys
@@ -63,6 +64,62 @@ def test_long_fused_batch_matches_oracle(T):
             assert e <= 1e-5, (T, i, d, e)
     _say("long fused worst rel L2 %.3e" % worst)
     assert (st.cpu().numpy() & ~gwgen.STATUS_CUT_AT_NYQUIST).max() == 0
+
+
+def test_long_full_size_sampled():
+    """Batch 256 of 256 s windows (N = 2^19) after the autotuner, as the
+    benchmark launches it; four samples checked against the oracle in full
+    and the whole batch for finite output and status bits."""
+    cfg = inputs.config("bns_long")
+    N = int(cfg["t_window"] * cfg["fs"])
+    B = cfg["batch"]
+    bg_np = bg_for(2048.0, 22)
+    bg = torch.from_numpy(bg_np).to(DEV)
+    gen = gwgen.Generator(cfg)
+    out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
+    st = torch.zeros(B, dtype=torch.int32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("long full size B=%d N=%d" % (B, N))
+    gen.autotune(B, bg, out, ws, reps=1)
+    gen.generate_batch(2, 0, B, bg, out, ws, status=st)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O = params.cpu().numpy(), offs.cpu().numpy()
+    worst = 0.0
+    for i in (0, 1, B // 2, B - 1):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        got = out[i].cpu().numpy()
+        for d in range(3):
+            e = rel_l2(got[d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("long full size worst rel L2 %.3e" % worst)
+    assert bool(torch.isfinite(out).all())
+    assert (st.cpu().numpy() & ~gwgen.STATUS_CUT_AT_NYQUIST).max() == 0
+
+
+def test_long_sine_gaussian_matches_oracle():
+    """Sine-Gaussian bursts in 64 s windows (N = 2^17, four-step path)."""
+    cfg = inputs.config("sine_gaussian", t_window=64.0)
+    N = int(cfg["t_window"] * cfg["fs"])
+    bg_np = bg_for(2048.0, 22)
+    gen = gwgen.Generator(cfg)
+    B = 3
+    out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("long sine-Gaussian N=%d" % N)
+    gen.generate_batch(9, 0, B, torch.from_numpy(bg_np).to(DEV), out, ws)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        for d in range(3):
+            e = rel_l2(G[i, d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("long sine-Gaussian worst rel L2 %.3e" % worst)
 
 
 def test_long_inject_and_whiten_steps_match_oracle():
