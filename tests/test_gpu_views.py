@@ -69,6 +69,33 @@ def test_view_pairs_match_oracle(name):
     _say("view pairs worst rel L2 %.3e" % worst)
 
 
+def test_view_pairs_full_size_sampled():
+    """The benchmark's batch of 2048 pairs at the paper-scale shape; four
+    pairs checked against the oracle, the whole batch for finite output."""
+    cfg = inputs.config("paper_scale")
+    bg_np = bg_for("paper_scale", 22)
+    gen = gwgen.Generator(cfg)
+    B, D, N = cfg["batch"], gen.sizes["D"], gen.sizes["N"]
+    bg = torch.from_numpy(bg_np).to(DEV)
+    ref_t = torch.empty((B, D, N), dtype=torch.float32, device=DEV)
+    shf_t = torch.empty_like(ref_t)
+    ws = gen.alloc_workspace(B)
+    _say("view pairs full size B=%d" % B)
+    gen.generate_batch_pairs(3, 0, B, bg, ref_t, shf_t, ws)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(ref_t).all()) and bool(torch.isfinite(shf_t).all())
+    p, o = priors.sample_params(cfg, 3, 0, B, bg_np.shape[1])
+    worst = 0.0
+    for i in (0, 1, B // 2, B - 1):
+        d_ref, d_shf = pipeline.generate_pair(cfg, bg_np, p[:, i], int(o[i]))
+        g_ref, g_shf = ref_t[i].cpu().numpy(), shf_t[i].cpu().numpy()
+        for d in range(D):
+            e = max(rel_l2(g_ref[d], d_ref[d]), rel_l2(g_shf[d], d_shf[d]))
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("view pairs full size worst rel L2 %.3e" % worst)
+
+
 @pytest.mark.parametrize("ext_k", [1, 4])
 def test_oversampled_batch_matches_oracle(ext_k):
     cfg = inputs.config("paper_scale")
