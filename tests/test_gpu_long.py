@@ -122,6 +122,33 @@ def test_long_sine_gaussian_matches_oracle():
     _say("long sine-Gaussian worst rel L2 %.3e" % worst)
 
 
+def test_long_binary32_mode_transforms():
+    """Precision mode 0 (binary32 phase) on the four-step path: with the
+    sources placed so far away that the signal is below 1e-12 of the noise,
+    the whitened windows test the binary32 transforms, Welch sums and gains
+    against the oracle at the usual bar; the phase precision is irrelevant."""
+    cfg = inputs.config("bns_long", t_window=64.0, precision=0, dl=(1e12, 2e12))
+    N = int(cfg["t_window"] * cfg["fs"])
+    bg_np = bg_for(2048.0, 22)
+    gen = gwgen.Generator(cfg)
+    B = 2
+    out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("long binary32 mode N=%d" % N)
+    gen.generate_batch(4, 0, B, torch.from_numpy(bg_np).to(DEV), out, ws)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        for d in range(3):
+            e = rel_l2(G[i, d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (i, d, e)
+    _say("long binary32 mode worst rel L2 %.3e" % worst)
+
+
 def test_long_inject_and_whiten_steps_match_oracle():
     cfg = inputs.config("bns_long", t_window=128.0)
     bg_np = bg_for(2048.0, 22)
