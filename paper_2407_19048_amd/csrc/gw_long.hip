@@ -157,83 +157,125 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rows(LongArgs a) {
   for (int e = 0; e < 16; ++e) row[fft_out_index<kN1, 0>(t, e)] = {v[e].x, v[e].y};
 }
 
-// Bins: one thread per pair (k, NC - k), k in [0, NC/2].  SRC 0 whitens,
-// SRC 1 adds the in-register signal and whitens, SRC 2 packs the given
-// projected spectrum (inject).
-// SRC 0, 1: grid (N1/256, B*D, N2/2 + 1); thread (k1, r) takes the element
-// at row r, column k1 of X'[k2][k1] = X[k2 + N2 k1], i.e. k = r + N2 k1, or
-// its mirror NC - k (row N2 - r, column N1 - 1 - k1) when k > NC/2, so that
-// a wavefront reads and writes runs of consecutive (or reversed) columns of
-// two rows, and reads the bin tables in the same transposed layout.  Rows 0
-// and N2/2 pair with themselves and use half their columns.
-// SRC 2 reads hdet by k: grid (ceil((NC/2 + 1)/256), B*D, 1), k = thread.
+// Inject: pack the given projected spectrum for the inverse transform, one
+// thread per pair (k, NC - k), k in [0, NC/2], reading hdet by k:
+// grid (ceil((NC/2 + 1)/256), B*D).  The packed pair lands at its place in
+// the transposed layout X'[k2][k1] = X[k2 + N2 k1] of the inverse rows.
+__global__ __launch_bounds__(256) void k_long_inject(LongArgs a, const float* hdet) {
+  const int64_t bd = blockIdx.y;
+  const int NC = a.NC, N2 = a.N2;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k > NC / 2) return;
+  float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
+  const int km = NC - k;
+  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
+  const cpx<float> W = reinterpret_cast<const cpx<float>*>(a.twr)[k];  // exp(-2 pi i k / N)
+  const float2* h = reinterpret_cast<const float2*>(hdet) + bd * (NC + 1);
+  const float2 h0 = h[k], h1 = h[km];
+  // irfft ignores Im at DC and Nyquist
+  const cpx<float> Yk = {h0.x, k == 0 ? 0.f : h0.y};
+  const cpx<float> Ym = {h1.x, k == 0 ? 0.f : h1.y};
+  const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
+  const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W);
+  buf[pos(k)] = {p.x - q.y, p.y + q.x};
+  if (k != 0 && km != k) buf[pos(km)] = {p.x + q.y, -p.y + q.x};
+}
+
+// Bins: the real-spectrum unpack of each pair (k, NC - k), k in [0, NC/2],
+// then (SRC 1) the in-register signal, the whitening gain and the repack for
+// the inverse; SRC 0 whitens only.  Thread (k1, r) takes the element at row
+// r, column k1 of X'[k2][k1] = X[k2 + N2 k1], i.e. k = r + N2 k1, or its
+// mirror NC - k (row N2 - r, column N1 - 1 - k1) when k > NC/2, so that a
+// wavefront reads and writes runs of consecutive (or reversed) columns of two
+// rows, and reads the bin tables in the same transposed layout.  Rows 0 and
+// N2/2 pair with themselves and use half their columns.  Two pairs per
+// thread, columns k1 and k1 + 256 (grid (N1/512, B*D, N2/2 + 1)): both pairs'
+// inputs are loaded before either is computed, so the second pair's loads
+// overlap the first pair's arithmetic.  Idle lanes load a real pair too (k is
+// clamped into range) and only skip their stores.
 template <class TP, int SRC>
-__global__ __launch_bounds__(256) void k_long_bins(LongArgs a, const float* hdet) {
+__global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
+  static_assert(SRC == 0 || SRC == 1, "whiten or fused");
+  constexpr int J = 2;
   const int64_t bd = blockIdx.y;
   const DevCfg& cf = a.w.cf;
   const int NC = a.NC, N2 = a.N2;
-  int k;
-  bool valid;
-  if constexpr (SRC == 2) {
-    k = blockIdx.x * 256 + threadIdx.x;
-    valid = k <= NC / 2;
-  } else {
-    const int k1 = blockIdx.x * 256 + threadIdx.x;  // < N1
-    const int r = blockIdx.z;
-    const int kr = r + N2 * k1;
-    valid = (r == 0) ? (k1 <= kN1 / 2) : (2 * r == N2) ? (k1 < kN1 / 2) : true;
-    k = min(kr, NC - kr);
-  }
+  const int r = blockIdx.z;
+  const int64_t b = bd / cf.n_det;
+  const int d = int(bd - b * cf.n_det);
+  float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
+  const float* psd = a.w.psd + bd * cf.Fw;
+  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
   __shared__ uint32_t sflag;
   if (threadIdx.x == 0) sflag = 0u;
   __syncthreads();
-  if (valid) {
-    const int64_t b = bd / cf.n_det;
-    const int d = int(bd - b * cf.n_det);
-    float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
-    const int km = NC - k;
-    // X[kk] sits at X'[kk mod N2][kk / N2]
-    auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
-    // exp(-2 pi i k / N)
-    const cpx<float> W = (SRC == 2) ? reinterpret_cast<const cpx<float>*>(a.twr)[k] : a.twr_t[pos(k)];
-    uint32_t flag = 0;
-    cpx<float> Yk, Ym;
-    if constexpr (SRC == 2) {
-      const float2* h = reinterpret_cast<const float2*>(hdet) + bd * (NC + 1);
-      const float2 h0 = h[k], h1 = h[km];
-      Yk = {h0.x, k == 0 ? 0.f : h0.y};
-      Ym = {h1.x, k == 0 ? 0.f : h1.y};
-    } else {
-      const float2 qa = buf[pos(k)], qb = buf[pos(km)];
-      const cpx<float> A = {qa.x, qa.y}, Bm = {qb.x, qb.y};
-      const cpx<float> s = cadd(A, cconj(Bm));
-      const cpx<float> u = cmul(W, csub(A, cconj(Bm)));
-      cpx<float> Xk = {0.5f * (s.x + u.y), 0.5f * (s.y - u.x)};
-      cpx<float> Xm = {0.5f * (s.x - u.y), 0.5f * (-s.y - u.x)};
-      if constexpr (SRC == 1) {
-        const WfScalars wsh = load_const(a.w.wf + b);
-        const DetScalars dsh = load_const(a.w.dsc + (b * cf.n_det + d));
-        const float cpl = float(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
-        const float cxx = float(dsh.fx * wsh.cosi);
-        const double tauT = dsh.tau * cf.invT;
-        const int64_t pk = pos(k), pm = pos(km);
-        const double kck = a.kc_t[pk], lkk = a.lk_t[pk], kcm = a.kc_t[pm], lkm = a.lk_t[pm];
-        Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, k, kck, lkk));
-        if (km != k) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, kcm, lkm));
-      }
-      const float* psd = a.w.psd + bd * cf.Fw;
-      Yk = cscale(Xk, whiten_gain<float>(cf, psd, k, NC, flag));
-      Ym = cscale(Xm, whiten_gain<float>(cf, psd, km, NC, flag));
-      if (km == k) Ym = Yk;
+  int k[J];
+  bool ok[J];
+  float2 qa[J], qb[J];
+  cpx<float> W[J];
+  float g[J][4];
+  double kc[J][2], lk[J][2];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int k1 = blockIdx.x * (256 * J) + 256 * j + threadIdx.x;  // < N1
+    const int kr = r + N2 * k1;
+    ok[j] = (r == 0) ? (k1 <= kN1 / 2) : (2 * r == N2) ? (k1 < kN1 / 2) : true;
+    k[j] = min(kr, NC - kr);
+    const int km = NC - k[j];
+    const int64_t pk = pos(k[j]), pm = pos(km);
+    qa[j] = buf[pk];
+    qb[j] = buf[pm];
+    W[j] = a.twr_t[pk];
+    const int ia = psd_index(cf, k[j], NC), ib = psd_index(cf, km, NC);
+    g[j][0] = psd[ia];
+    g[j][1] = psd[ia + 1];
+    g[j][2] = psd[ib];
+    g[j][3] = psd[ib + 1];
+    if constexpr (SRC == 1) {
+      kc[j][0] = a.kc_t[pk];
+      lk[j][0] = a.lk_t[pk];
+      kc[j][1] = a.kc_t[pm];
+      lk[j][1] = a.lk_t[pm];
     }
-    const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
-    const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W);
-    buf[pos(k)] = {p.x - q.y, p.y + q.x};
-    if (k != 0 && km != k) buf[pos(km)] = {p.x + q.y, -p.y + q.x};
-    if (flag) atomicOr(&sflag, flag);
   }
+  float cpl = 0.f, cxx = 0.f;
+  double tauT = 0.0;
+  WfScalars wsh;
+  if constexpr (SRC == 1) {
+    wsh = load_const(a.w.wf + b);
+    const DetScalars dsh = load_const(a.w.dsc + (b * cf.n_det + d));
+    cpl = float(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
+    cxx = float(dsh.fx * wsh.cosi);
+    tauT = dsh.tau * cf.invT;
+  }
+  uint32_t flag = 0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int kk = k[j], km = NC - kk;
+    const cpx<float> A = {qa[j].x, qa[j].y}, Bm = {qb[j].x, qb[j].y};
+    const cpx<float> s = cadd(A, cconj(Bm));
+    const cpx<float> u = cmul(W[j], csub(A, cconj(Bm)));
+    cpx<float> Xk = {0.5f * (s.x + u.y), 0.5f * (s.y - u.x)};
+    cpx<float> Xm = {0.5f * (s.x - u.y), 0.5f * (-s.y - u.x)};
+    if constexpr (SRC == 1) {
+      Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, kk, kc[j][0], lk[j][0]));
+      if (km != kk) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, kc[j][1], lk[j][1]));
+    }
+    uint32_t fj = 0;
+    const cpx<float> Yk = cscale(Xk, whiten_gain_at<float>(cf, g[j][0], g[j][1], kk, NC, fj));
+    cpx<float> Ym = cscale(Xm, whiten_gain_at<float>(cf, g[j][2], g[j][3], km, NC, fj));
+    if (km == kk) Ym = Yk;
+    const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
+    const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W[j]);
+    if (ok[j]) {
+      buf[pos(kk)] = {p.x - q.y, p.y + q.x};
+      if (kk != 0 && km != kk) buf[pos(km)] = {p.x + q.y, -p.y + q.x};
+      flag |= fj;
+    }
+  }
+  if (flag) atomicOr(&sflag, flag);
   __syncthreads();
-  if (threadIdx.x == 0 && sflag && a.w.status) atomicOr(a.w.status + bd / cf.n_det, sflag);
+  if (threadIdx.x == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
 }
 
 template <int SRC>
@@ -287,11 +329,11 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   if (items <= 0) return GW_OK;
   if (items > 65535) return ctx_fail(c, GW_EINVAL, "long windows: at most 65535 (sample, detector) items per call");
   if (!c->long_tabs) return ctx_fail(c, GW_EUNSUPPORTED, "long windows need the binary32 tables");
-  const dim3 bins_grid(unsigned(kN1 / 256), unsigned(items), unsigned(a.N2 / 2 + 1));
+  const dim3 bins_grid(unsigned(kN1 / 512), unsigned(items), unsigned(a.N2 / 2 + 1));
   const dim3 inject_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
   const dim3 rows_grid(unsigned(items * a.N2));
   if (src == 2) {
-    hipLaunchKernelGGL((k_long_bins<double, 2>), inject_grid, dim3(256), 0, st, a, hdet);
+    hipLaunchKernelGGL(k_long_inject, inject_grid, dim3(256), 0, st, a, hdet);
     hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
     launch_cols_inv<2>(a, items, st);
     return ctx_check_launch(c, "long inject");
@@ -300,11 +342,11 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   else launch_cols_fwd<1>(a, items, st);
   hipLaunchKernelGGL((k_long_rows<-1>), rows_grid, dim3(kN1 / 16), 0, st, a);
   if (src == 0) {
-    hipLaunchKernelGGL((k_long_bins<double, 0>), bins_grid, dim3(256), 0, st, a, nullptr);
+    hipLaunchKernelGGL((k_long_bins<double, 0>), bins_grid, dim3(256), 0, st, a);
   } else if (d.precision == 0) {
-    hipLaunchKernelGGL((k_long_bins<float, 1>), bins_grid, dim3(256), 0, st, a, nullptr);
+    hipLaunchKernelGGL((k_long_bins<float, 1>), bins_grid, dim3(256), 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_long_bins<double, 1>), bins_grid, dim3(256), 0, st, a, nullptr);
+    hipLaunchKernelGGL((k_long_bins<double, 1>), bins_grid, dim3(256), 0, st, a);
   }
   hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
   launch_cols_inv<0>(a, items, st);
