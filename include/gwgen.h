@@ -178,6 +178,8 @@ gw_status inject(gw_ctx* ctx, const float* bg, int64_t L_bg,
  * scaling:
  *   psd[k] = c_k/(K fs sum w^2) sum_s |rfft(w seg_s)[k]|^2,
  * with c_k = 2 except at DC and Nyquist, where c_k = 1.
+ * offset: int64 [B] device array; the host does not read it, so its values
+ * must lie in [0, L_bg - P] (sample_params draws them in [0, L_bg - P - N]).
  * psd: float [B][n_det][L/2+1]. */
 gw_status welch_psd(gw_ctx* ctx, const float* bg, int64_t L_bg,
                     const int64_t* offset, int64_t B, float* psd,
@@ -233,8 +235,12 @@ gw_status gw_run_psd(gw_ctx* ctx, const float* bg, int64_t L_bg, int64_t n_chunk
  * f_min, at DC and at Nyquist), its impulse response (inverse real
  * transform of length N) multiplied by cos^2(pi n / M) for circular lags
  * |n| < M/2 and by 0 elsewhere, then the magnitude of the forward transform.
- * filt: float [n_det][N/2+1].  M even, 2 <= M < N (M = fduration * fs). */
-gw_status gw_whiten_filter(gw_ctx* ctx, const float* psd, int64_t M, float* filt, hipStream_t stream);
+ * filt: float [n_det][N/2+1].  M even, 2 <= M < N (M = fduration * fs).
+ * status: uint32 [n_det] or NULL; overwritten with each detector's
+ * GW_STATUS_NONFINITE_PSD / GW_STATUS_NONPOSITIVE_PSD bits (such bins get
+ * zero gain before truncation). */
+gw_status gw_whiten_filter(gw_ctx* ctx, const float* psd, int64_t M, float* filt, uint32_t* status,
+                           hipStream_t stream);
 /* gw_generate_batch with the fixed filters in place of per-sample Welch
  * PSDs: same prior draws and windows (same seed gives the same parameters
  * and offsets), whitening Y_k = X_k filt[d][k], and the first and last

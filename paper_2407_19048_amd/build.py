@@ -1,5 +1,8 @@
 """Build libgwgen.so in-tree for gfx950 with hipcc.
 
+Each translation unit is compiled to an object file in its own hipcc
+process (in parallel), then the objects are linked into the shared library.
+
     python -m paper_2407_19048_amd.build
 """
 
@@ -8,11 +11,13 @@ import subprocess
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(_HERE, "csrc", n) for n in ("gwgen.hip", "gw_ragged.hip", "gw_long.hip", "gw_surrogate.hip")]
+SRC_NAMES = ("gwgen.hip", "gw_ragged.hip", "gw_long.hip", "gw_surrogate.hip")
+SRCS = [os.path.join(_HERE, "csrc", n) for n in SRC_NAMES]
 OUT = os.path.join(_HERE, "libgwgen.so")
+OBJ_DIR = os.path.join(os.path.dirname(_HERE), "_build")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
@@ -20,14 +25,31 @@ HIPCC_FLAGS = [
 
 def build(verbose=True):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs, procs = [], []
+    for src in SRCS:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmd = [hipcc] + HIPCC_FLAGS + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    failed = []
+    for src, p in zip(SRCS, procs):
+        text, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(text)
+            failed.append((os.path.basename(src), p.returncode))
+    if failed:
+        raise RuntimeError("hipcc failed: %s" % ", ".join("%s (status %d)" % f for f in failed))
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + SRCS
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed with status %d" % r.returncode)
+        raise RuntimeError("link failed with status %d" % r.returncode)
     os.replace(tmp, OUT)
     return OUT
 

@@ -283,7 +283,8 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   bool use_surr = false;
   const float* nd = nullptr;
   if constexpr (SRC == 3) {
-    use_surr = !(load_const(a.logmm + b) > a.logmm_max);
+    // a NaN prediction fails the test and falls back to the plain model
+    use_surr = load_const(a.logmm + b) <= a.logmm_max;
     nd = a.nodes + b * 2 * kSurrNodes;
     if (snodes) nd = snodes;  // staged before the forward transform
     if (active && !use_surr && t == 0 && d == 0 && a.status)

@@ -772,14 +772,15 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
   std::fill(ms, ms + 12, 1e300);  // best of kTuneRounds interleaved rounds
   auto time_stage = [&](int stage, double* res) {
     s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, stage, st);  // warm-up
-    (void)hipEventRecord(e0, st);
+    if (s == GW_OK && hipEventRecord(e0, st) != hipSuccess) s = rfail(r, GW_EHIP, "hipEventRecord");
     for (int k = 0; k < reps && s == GW_OK; ++k)
       s = enqueue_ragged(r, 1, 0, false, bg, L_bg, span, out, nullptr, nullptr, workspace, stage, st);
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess && s == GW_OK) s = rfail(r, GW_EHIP, "hipEventSynchronize");
+    if (s == GW_OK && hipEventRecord(e1, st) != hipSuccess) s = rfail(r, GW_EHIP, "hipEventRecord");
+    if (s == GW_OK && hipEventSynchronize(e1) != hipSuccess) s = rfail(r, GW_EHIP, "hipEventSynchronize");
+    // a failed timing query fails the tuner rather than reading as 0 ms
     float t = 0.f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    *res = std::min(*res, double(t) / reps);
+    if (s == GW_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) s = rfail(r, GW_EHIP, "hipEventElapsedTime");
+    if (s == GW_OK) *res = std::min(*res, double(t) / reps);
   };
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     s = rfail(r, GW_EHIP, "hipEventCreate");

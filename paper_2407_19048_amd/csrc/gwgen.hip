@@ -241,6 +241,7 @@ struct FiltArgs {
   int M;
   const void* tw;    // cpx<T>[NC]
   const void* twr;   // cpx<T>[NC/2 + 1]
+  uint32_t* status;  // [D] GW_STATUS_* bits of each detector's PSD, or NULL
 };
 
 template <class T, int NC>
@@ -256,6 +257,8 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
   const cpx<T>* twr = reinterpret_cast<const cpx<T>*>(a.twr);
   PowTwiddle<T, NC, 0> tw{reinterpret_cast<const cpx<T>*>(a.tw)};
   uint32_t flag = 0;
+  __shared__ uint32_t dflag;  // the detector's status bits (visible after the first barrier)
+  if (t == 0) dflag = 0u;
   // 1. g is real and even: pack it for the half-length inverse transform
   for (int i = 0; i <= 8; ++i) {
     const int k = t + NT * i;
@@ -330,7 +333,10 @@ __global__ __launch_bounds__(NC / 16) void k_filter(FiltArgs a) {
     out[k] = float(fabs(T(0.5) * (s.x + u.y)));
     if (km != k) out[km] = float(fabs(T(0.5) * (s.x - u.y)));
   }
-  (void)flag;
+  // bins with a non-finite or non-positive PSD were dropped from the gain
+  if (flag) atomicOr(&dflag, flag);
+  __syncthreads();
+  if (t == 0 && a.status) a.status[d] = dflag;
 }
 
 }  // namespace
@@ -1138,14 +1144,15 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
   const int saved[3] = {c->dc.ord_welch, c->dc.occ_welch, c->dc.ord_win};
   auto time_stage = [&](int mask, double* res) {
     s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);  // warm-up
-    (void)hipEventRecord(e0, st);
+    if (s == GW_OK && hipEventRecord(e0, st) != hipSuccess) s = fail(c, GW_EHIP, "hipEventRecord");
     for (int r = 0; r < reps && s == GW_OK; ++r)
       s = enqueue_batch(c, 1, 0, nullptr, B, bg, L_bg, out, nullptr, nullptr, workspace, mask, st);
-    (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess && s == GW_OK) s = fail(c, GW_EHIP, "hipEventSynchronize");
+    if (s == GW_OK && hipEventRecord(e1, st) != hipSuccess) s = fail(c, GW_EHIP, "hipEventRecord");
+    if (s == GW_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(c, GW_EHIP, "hipEventSynchronize");
+    // a failed timing query fails the tuner rather than reading as 0 ms
     float t = 0.f;
-    (void)hipEventElapsedTime(&t, e0, e1);
-    *res = std::min(*res, double(t) / reps);
+    if (s == GW_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) s = fail(c, GW_EHIP, "hipEventElapsedTime");
+    if (s == GW_OK) *res = std::min(*res, double(t) / reps);
   };
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     s = fail(c, GW_EHIP, "hipEventCreate");
@@ -1220,14 +1227,16 @@ gw_status gw_run_psd(gw_ctx* c, const float* bg, int64_t L_bg, int64_t n_chunks,
   return check_launch(c, "k_mean_chunks");
 }
 
-gw_status gw_whiten_filter(gw_ctx* c, const float* psd, int64_t M, float* filt, hipStream_t stream) {
+gw_status gw_whiten_filter(gw_ctx* c, const float* psd, int64_t M, float* filt, uint32_t* status,
+                           hipStream_t stream) {
   GW_CHECK_CTX(c);
   const DevCfg& d = c->dc;
   if (!psd || !filt) return fail(c, GW_EINVAL, "NULL pointer");
   if (!aligned4(psd) || !aligned4(filt)) return fail(c, GW_EINVAL, "misaligned pointer");
   if (M < 2 || M >= d.N || (M & 1)) return fail(c, GW_EINVAL, "M must be even with 2 <= M < N");
   if (d.N > 32768) return fail(c, GW_EUNSUPPORTED, "the per-run filter needs N <= 32768");
-  FiltArgs a{d, psd, filt, int(M), c->tw_win, c->twr_win};
+  if (status && !aligned4(status)) return fail(c, GW_EINVAL, "misaligned pointer");
+  FiltArgs a{d, psd, filt, int(M), c->tw_win, c->twr_win, status};
   if (d.precision == 2) launch_filter<double>(d, a, stream);
   else launch_filter<float>(d, a, stream);
   return check_launch(c, "k_filter");

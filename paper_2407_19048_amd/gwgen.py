@@ -132,7 +132,7 @@ def lib():
             "gw_ragged_autotune": ([vp, vp, vp, vp, vp, i64, i32, vp], i32),
             "gw_run_psd_workspace_size": ([vp, i64, ctypes.POINTER(i64)], i32),
             "gw_run_psd": ([vp, vp, i64, i64, vp, vp, i64, vp], i32),
-            "gw_whiten_filter": ([vp, vp, i64, vp, vp], i32),
+            "gw_whiten_filter": ([vp, vp, i64, vp, vp, vp], i32),
             "gw_generate_batch_runpsd": ([vp, u64, u64, i64, vp, i64, vp, i64, vp, vp, vp, vp, i64, vp], i32),
             "gw_generate_batch_pairs": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp, vp, i64, vp], i32),
             "gw_generate_batch_oversampled": ([vp, u64, u64, i64, i32, vp, i64, vp, vp, vp, vp, i64, vp], i32),
@@ -251,6 +251,7 @@ class Generator:
     def project_detectors(self, params, hp, hc, hdet):
         import torch
         B = params.shape[1]
+        _want(params, torch.float64, (N_PARAMS, B), "params")
         _want(hdet, torch.complex64, (B, self.sizes["D"], self.sizes["F"]), "hdet")
         _want(hp, torch.complex64, (B, self.sizes["F"]), "hp")
         _want(hc, torch.complex64, (B, self.sizes["F"]), "hc")
@@ -260,6 +261,7 @@ class Generator:
     def inject(self, bg, offset, hdet, strain):
         import torch
         B = offset.shape[0]
+        _want(offset, torch.int64, (B,), "offset")
         _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
         _want(hdet, torch.complex64, (B, self.sizes["D"], self.sizes["F"]), "hdet")
         _want(strain, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "strain")
@@ -269,6 +271,7 @@ class Generator:
     def welch_psd(self, bg, offset, psd):
         import torch
         B = offset.shape[0]
+        _want(offset, torch.int64, (B,), "offset")
         _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
         _want(psd, torch.float32, (B, self.sizes["D"], self.sizes["Fw"]), "psd")
         self._check(lib().welch_psd(self._h, _ptr(bg), bg.shape[1], _ptr(offset), B, _ptr(psd),
@@ -395,11 +398,14 @@ class Generator:
                                      v.value, _stream()), "gw_run_psd")
         return ws  # keep alive until the stream has run
 
-    def whiten_filter(self, psd, M, filt):
+    def whiten_filter(self, psd, M, filt, status=None):
         import torch
         _want(psd, torch.float32, (self.sizes["D"], self.sizes["Fw"]), "psd")
         _want(filt, torch.float32, (self.sizes["D"], self.sizes["F"]), "filt")
-        self._check(lib().gw_whiten_filter(self._h, _ptr(psd), int(M), _ptr(filt), _stream()), "gw_whiten_filter")
+        if status is not None:
+            _want(status, torch.int32, (self.sizes["D"],), "status")
+        self._check(lib().gw_whiten_filter(self._h, _ptr(psd), int(M), _ptr(filt), _ptr(status), _stream()),
+                    "gw_whiten_filter")
 
     def generate_batch_runpsd(self, seed, batch_index, B, bg, filt, crop, out, workspace, params_f32=None,
                               status=None):

@@ -12,6 +12,7 @@ import pytest
 import oracle
 from oracle import pipeline
 from paper_2407_19048_amd import gwgen, inputs
+from draws import checked_draws
 
 torch = pytest.importorskip("torch")
 
@@ -55,6 +56,7 @@ def test_long_fused_batch_matches_oracle(T):
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
     P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    P, O = checked_draws(cfg, 5, 1 * B, P, O, bg_np.shape[1])
     worst = 0.0
     for i in range(B):
         ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
@@ -85,8 +87,10 @@ def test_long_full_size_sampled():
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
     P, O = params.cpu().numpy(), offs.cpu().numpy()
+    idx = (0, 1, B // 2, B - 1)
+    P, O = checked_draws(cfg, 2, 0, P, O, bg_np.shape[1], idx=idx)
     worst = 0.0
-    for i in (0, 1, B // 2, B - 1):
+    for i in idx:
         ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
         got = out[i].cpu().numpy()
         for d in range(3):
@@ -112,6 +116,7 @@ def test_long_sine_gaussian_matches_oracle():
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
     P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    P, O = checked_draws(cfg, 9, 0, P, O, bg_np.shape[1])
     worst = 0.0
     for i in range(B):
         ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
@@ -139,6 +144,7 @@ def test_long_binary32_mode_transforms():
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
     P, O, G = params.cpu().numpy(), offs.cpu().numpy(), out.cpu().numpy()
+    P, O = checked_draws(cfg, 4, 0, P, O, bg_np.shape[1])
     worst = 0.0
     for i in range(B):
         ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
@@ -171,7 +177,7 @@ def test_long_inject_and_whiten_steps_match_oracle():
     out = torch.empty_like(strain)
     gen.whiten(strain, psd, out)
     torch.cuda.synchronize()
-    P, O = params.cpu().numpy(), offs.cpu().numpy()
+    P, O = checked_draws(cfg, 7, 0, params.cpu().numpy(), offs.cpu().numpy(), bg_np.shape[1])
     S, W = strain.cpu().numpy(), out.cpu().numpy()
     for i in range(B):
         ref, stg = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]), return_stages=True)

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from paper_2407_19048_amd import gwgen, inputs
+from draws import checked_draws
 
 torch = pytest.importorskip("torch")
 
@@ -174,7 +175,7 @@ def test_fused_batch_matches_oracle(name, B, log2):
     np.testing.assert_array_equal(offs, o_o)
     np.testing.assert_allclose(params, p_o, rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(pf, p_o.astype(np.float32), rtol=2e-7, atol=1e-30)
-    errs = check_fused_against_oracle(cfg, bg, out, params, offs, range(B))
+    errs = check_fused_against_oracle(cfg, bg, out, p_o, o_o, range(B))
     _say("rel L2: max %.3e median %.3e" % (errs.max(), np.median(errs)))
     assert errs.max() < TOL_STRAIN
     # fused path equals the six steps composed
@@ -195,7 +196,9 @@ def test_fused_full_size_sampled():
     out, pf, status, params, offs = fused(gen, bg_t, 2, 0, B)
     assert np.all(np.isfinite(out))
     idx = list(range(0, B, B // 14)) + [B - 1]
-    errs = check_fused_against_oracle(cfg, bg, out, params, offs, idx)
+    # the oracle draws its own parameters; the GPU's must be the same numbers
+    P, O = checked_draws(cfg, 2, 0, params, offs, bg.shape[1], idx=idx)
+    errs = check_fused_against_oracle(cfg, bg, out, P, O, idx)
     _say("rel L2 sampled: max %.3e median %.3e" % (errs.max(), np.median(errs)))
     assert errs.max() < TOL_STRAIN
     # whitened noise: per-window variance close to the expected level
@@ -295,8 +298,9 @@ def test_signal_only_whitened_with_true_psd():
     torch.cuda.synchronize()
     o = out.cpu().numpy()
     errs = []
+    P, _ = checked_draws(cfg, 31, 0, g["params"], g["offs"], bg.shape[1])
     for i in range(B):
-        p = g["params"][:, i]
+        p = P[:, i]
         hp, hc = oracle.pipeline.waveform_on_grid(cfg, p)
         H = oracle.project_detectors(cfg, p, hp, hc)
         y = oracle.inject(cfg, np.zeros((3, z["P"] + z["N"])), 0, H)
@@ -320,7 +324,8 @@ def test_precision_modes(prec):
     bg = background(name, 22)
     B = 6
     out, pf, status, params, offs = fused(gen, gpu_tensor(bg), 2, 0, B)
-    errs = check_fused_against_oracle(cfg, bg, out, params, offs, range(B))
+    P, O = checked_draws(cfg, 2, 0, params, offs, bg.shape[1])
+    errs = check_fused_against_oracle(cfg, bg, out, P, O, range(B))
     _say("precision %d: max %.3e median %.3e" % (prec, errs.max(), np.median(errs)))
     if prec == 2:
         assert errs.max() < 2e-7  # binary64 throughout, output rounded to binary32

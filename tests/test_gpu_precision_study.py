@@ -89,8 +89,12 @@ def test_precision_study(study_inputs):
         if refs is None:
             refs = []
             for i in idx:
-                p = g["params"][:, i]
-                out, st = oracle.generate_sample(cfg, bg, p, int(g["offs"][i]), return_stages=True)
+                # the oracle's own draw, checked against the GPU's first
+                p, o = oracle.sample_params(cfg, 2, i, 1, bg.shape[1])
+                p, o = p[:, 0], int(o[0])
+                assert o == int(g["offs"][i])
+                np.testing.assert_allclose(g["params"][:, i], p, rtol=1e-12, atol=1e-12)
+                out, st = oracle.generate_sample(cfg, bg, p, o, return_stages=True)
                 y0 = oracle.inject(cfg, np.zeros((3, z["P"] + z["N"])), 0, st["H"])
                 Sw = oracle.interp_psd(g["S"].astype(np.float64), z["r"])
                 sig = np.stack([oracle.whiten(y0[d], Sw, cfg["fs"], cfg["f_min"]) for d in range(3)])

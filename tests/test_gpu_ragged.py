@@ -16,6 +16,7 @@ import pytest
 
 from oracle import pipeline
 from paper_2407_19048_amd import gwgen, inputs
+from draws import checked_draws
 
 torch = pytest.importorskip("torch")
 
@@ -266,7 +267,7 @@ def test_plain_kernel_variants_match_oracle(name):
         gen.generate_batch(5, 0, B, bg, out, ws)
         torch.cuda.synchronize()
         params, offs = gen.workspace_views(ws, B)
-        p, o = params.cpu().numpy(), offs.cpu().numpy()
+        p, o = checked_draws(cfg, 5, 0, params.cpu().numpy(), offs.cpu().numpy(), bg_np.shape[1])
         ref = oracle.generate_batch(cfg, bg_np, p, o)
         g = out.cpu().numpy()
         for i in range(B):
@@ -290,7 +291,8 @@ def test_autotuners_keep_results():
     gen.generate_batch(2, 0, B, bg, out, ws)
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
-    ref = oracle.generate_batch(cfg, bg_np, params.cpu().numpy()[:, :4], offs.cpu().numpy()[:4])
+    p, o = checked_draws(cfg, 2, 0, params.cpu().numpy(), offs.cpu().numpy(), bg_np.shape[1], idx=range(4))
+    ref = oracle.generate_batch(cfg, bg_np, p[:, :4], o[:4])
     g = out.cpu().numpy()
     for i in range(4):
         assert rel_l2(g[i], ref[i]) <= TOL_STRAIN

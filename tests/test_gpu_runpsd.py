@@ -84,6 +84,25 @@ def test_whiten_filter_matches_oracle(name, M):
         assert rel_l2(got[d], ref[d]) <= 1e-5, (d, rel_l2(got[d], ref[d]))
 
 
+def test_whiten_filter_status_bits():
+    """A NaN PSD bin in one detector and a zero bin in another are dropped
+    from the gain and reported per detector; the clean detector reports 0."""
+    cfg = inputs.config("paper_scale")
+    _, psd, _ = _oracle_filter_inputs(cfg, 3, 4096)
+    bad = psd.copy()
+    bad[0, 300] = np.nan   # 300 * df = 150 Hz, inside the kept band
+    bad[1, 500] = 0.0
+    gen = gwgen.Generator(cfg)
+    filt = torch.empty((gen.sizes["D"], gen.sizes["F"]), dtype=torch.float32, device=DEV)
+    status = torch.full((gen.sizes["D"],), -1, dtype=torch.int32, device=DEV)  # overwritten
+    gen.whiten_filter(_gpu(bad), 4096, filt, status)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy().astype(np.uint32)
+    _say("whiten filter status bits %s" % st.tolist())
+    assert st.tolist() == [gwgen.STATUS_NONFINITE_PSD, gwgen.STATUS_NONPOSITIVE_PSD, 0]
+    assert bool(torch.isfinite(filt).all())
+
+
 def _run_batch(gen, bg, filt, crop, B, seed=9, batch_index=1):
     N = gen.sizes["N"]
     out = torch.empty((B, gen.sizes["D"], N - 2 * crop), dtype=torch.float32, device=DEV)
@@ -126,8 +145,13 @@ def test_runpsd_full_size_sampled():
     gen = gwgen.Generator(cfg)
     B = 2048
     out, params, offs = _run_batch(gen, _gpu(bg_np), _gpu(filt.astype(np.float32)), crop, B, seed=2, batch_index=0)
+    # the GPU draws are the oracle's before they are handed to it
+    idx = np.array([0, 777, B - 1])
+    ref_p, ref_o = pipeline.sample_params(cfg, 2, 0, B, bg_np.shape[1])
+    np.testing.assert_allclose(params[:, idx], ref_p[:, idx], rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(offs, ref_o)
     f32 = filt.astype(np.float32).astype(np.float64)
-    for i in (0, 777, B - 1):
+    for i in idx:
         ref = pipeline.generate_sample_runpsd(cfg, bg_np, params[:, i], int(offs[i]), f32, crop)
         for d in range(3):
             assert rel_l2(out[i, d], ref[d]) <= 1e-5

@@ -652,3 +652,28 @@ def test_window_follows_psd_stretch():
         assert np.all(psd[0] == 0) and np.all(y[0] == 0)
         assert (np.abs(psd[1]).max() > 0) == in_psd
         assert (np.abs(y[1]).max() > 0) == (pos == o + z["P"])
+
+
+@pytest.mark.parametrize("mc,q", [(10.0, 1.0), (25.0, 0.5), (60.0, 0.25), (100.0, 0.125)])
+def test_frequency_cutoff_is_schwarzschild_isco_and_imr_end(mc, q):
+    """TaylorF2 stops at the gravitational-wave frequency of the innermost
+    stable circular orbit of a non-spinning hole of the binary's total mass:
+    twice the orbital frequency Omega/(2 pi), Omega = 1/(M (r^(3/2) + a)) on
+    the prograde circular Kerr orbit (Bardeen, Press & Teukolsky 1972) at
+    a = 0, r = r_ISCO.  The IMR-form model ends at M f = 0.2.  The total mass
+    is rebuilt here from its definition, M = m1 + m2 with
+    M_c = (m1 m2)^(3/5) / M^(1/5) and q = m2/m1, solved by bisection."""
+    r, _, _ = _kerr_isco(0.0)
+    lo, hi = mc, 100.0 * mc
+    for _ in range(200):
+        M = 0.5 * (lo + hi)
+        m1 = M / (1.0 + q)
+        m2 = q * m1
+        if (m1 * m2) ** 0.6 / M ** 0.2 < mc:
+            lo = M
+        else:
+            hi = M
+    Ms = 0.5 * (lo + hi) * 4.925490947641267e-6   # G Msun / c^3 [s]
+    f_isco = 2.0 * (1.0 / (Ms * (r ** 1.5 + 0.0))) / (2.0 * math.pi)
+    assert abs(waveform.frequency_cutoff(0, mc, q) / f_isco - 1.0) < 1e-12
+    assert abs(waveform.frequency_cutoff(1, mc, q) * Ms - 0.2) < 1e-12
