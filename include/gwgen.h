@@ -456,14 +456,26 @@ gw_status gw_surrogate_forward(gw_surrogate* s, const float* theta, int64_t B, f
  * summed squared error (device float[1] or NULL); no update */
 gw_status gw_surrogate_gradients(gw_surrogate* s, const float* theta, const float* z, int64_t B, float* grads,
                                  float* loss, hipStream_t stream);
-/* one AdamW step (beta 0.9/0.999, eps 1e-8) on a batch of B <= max_batch */
+/* One AdamW step (section 5.1 trains with AdamW; Loshchilov & Hutter 2019)
+ * on a batch of B <= max_batch: gradients of the mean-squared loss, moment
+ * estimates m, v with bias correction, then for every weight
+ *   p <- p - lr (m_hat / (sqrt(v_hat) + eps) + weight_decay p);
+ * biases are updated without the decay term.  lr >= 0, weight_decay >= 0.
+ * loss: device float[1] receiving the summed squared error, or NULL. */
 gw_status gw_surrogate_train_step(gw_surrogate* s, const float* theta, const float* z, int64_t B, float lr,
                                   float weight_decay, float* loss, hipStream_t stream);
+/* AdamW hyper-parameters (defaults beta1 0.9, beta2 0.999, eps 1e-8);
+ * 0 <= beta < 1, eps > 0.  Kept in the checkpoint. */
+gw_status gw_surrogate_set_adam(gw_surrogate* s, double beta1, double beta2, double eps);
 /* last hidden layer float [B][256] */
 gw_status gw_surrogate_hidden(gw_surrogate* s, const float* theta, int64_t B, float* h3, hipStream_t stream);
 gw_status gw_surrogate_set_head(gw_surrogate* s, const float* host_head, int64_t n);      /* 257 floats */
-/* ridge fit of the log10-mismatch head on h3 (device) and y (host); synchronous */
-gw_status gw_surrogate_fit_head(gw_surrogate* s, const float* h3, const float* y_host, int64_t n, double ridge);
+/* Ridge fit of the mismatch head (synchronous): the coefficients w of
+ * [h3 1] minimising ||[h3 1] w - y||^2 + ridge n ||w||^2 with
+ * y = log10(max(mm, 1e-12)).  h3: device float [n][256] (last hidden layer,
+ * gw_surrogate_hidden); mm: host double [n] measured mismatches (finite);
+ * ridge >= 0. */
+gw_status gw_surrogate_fit_head(gw_surrogate* s, const float* h3, const double* mm_host, int64_t n, double ridge);
 /* node values float [B][2][1024] and predicted log10 mismatch float [B] (or NULL) */
 gw_status gw_surrogate_nodes(gw_surrogate* s, const double* params, int64_t B, float* nodes, float* logmm,
                              hipStream_t stream);
@@ -495,7 +507,14 @@ gw_status gw_generate_batch_surrogate(gw_ctx* ctx, gw_surrogate* s, uint64_t see
  * head float [257] (weights: gw_surrogate_set_weights). */
 gw_status gw_surrogate_set_state(gw_surrogate* s, const float* basis, const double* mean, const float* A,
                                  const float* zmean, const float* zstd, const float* head);
-/* host file with basis, skip path, standardisation, head and weights */
+/* The same state copied to host arrays (synchronous). */
+gw_status gw_surrogate_get_state(gw_surrogate* s, float* basis, double* mean, float* A, float* zmean,
+                                 float* zstd, float* head);
+/* Host checkpoint file: basis, skip path, standardisation, head, weights and
+ * the optimiser state (AdamW moments, step counter, hyper-parameters), so
+ * that training resumed after gw_surrogate_load continues exactly as without
+ * the interruption.  Synchronous.  Load returns GW_EINVAL for a bad or
+ * truncated file. */
 gw_status gw_surrogate_save(gw_surrogate* s, const char* path);
 gw_status gw_surrogate_load(gw_surrogate* s, const char* path);
 

@@ -33,9 +33,28 @@ Readings:
   * Mismatch: <a|b> = 4 df Re sum_{kept} a_k conj(b_k) / S_k over
     f_min <= f_k < f_cut, 0 < k < N/2;  mm = 1 - <a|b>/sqrt(<a|a><b|b>).
 
+  * Reduced basis: the leading right singular vectors of the mean-removed
+    target rows, each with its largest-magnitude component made positive
+    (the singular vectors are unique only up to sign).
+  * Optimiser: AdamW (Loshchilov & Hutter, "Decoupled Weight Decay
+    Regularization", ICLR 2019), the optimiser section 5.1 of the paper
+    trains with: Adam's moment estimates with bias correction (Kingma & Ba
+    2015) and a weight decay applied to the weights themselves rather than
+    added to the gradient.  The step size lr multiplies both terms (the
+    decay per step is lr * weight_decay).  Biases are not decayed.
+  * Mismatch head: log10 of the mismatch predicted linearly from the last
+    hidden layer, bf16(silu(z3)) . w + w0, fitted by ridge least squares
+    with the penalty ridge * n on every coefficient (the constant too).
+  * Fallback routing: a sample keeps the surrogate only where the predicted
+    log10 mismatch is <= the threshold; a NaN prediction falls back.
+
 Pins: the MLP backward pass against central differences; basis truncation
-error equal to the discarded eigenvalue sum (Eckart-Young); mm(h, h) = 0 and
-invariance of mm to overall scale; small-phase-error law mm ~ Var_w(dpsi)/2.
+error equal to the discarded squared singular values (Eckart-Young) and no
+better basis among random ones; a rank-one case; mm(h, h) = 0 and
+invariance of mm to overall scale; small-phase-error law mm ~ Var_w(dpsi)/2;
+the first AdamW step by hand, equality with Adam in Kingma & Ba's rearranged
+form at zero decay, pure exponential decay of the weights at zero gradient;
+the ridge head against its normal equations and a hand-solved case.
 """
 
 import math
@@ -196,3 +215,63 @@ def mismatch(a, b, S, df, kept):
     if aa <= 0.0 or bb <= 0.0:
         return 0.0
     return 1.0 - ab / math.sqrt(aa * bb)
+
+
+# ------------------------------------------------------------ training pieces
+
+def reduced_basis(X, n_basis):
+    """(mean [n], V [n_basis][n]) of the rows of X: the column mean and the
+    leading right singular vectors of X - mean (numpy.linalg.svd), each row of
+    V with its largest-magnitude component positive."""
+    X = np.asarray(X, dtype=np.float64)
+    mean = X.mean(axis=0)
+    _, _, Vt = np.linalg.svd(X - mean, full_matrices=False)
+    V = Vt[:n_basis].copy()
+    big = V[np.arange(V.shape[0]), np.argmax(np.abs(V), axis=1)]
+    return mean, V * np.where(big < 0, -1.0, 1.0)[:, None]
+
+
+def truncation_error(X, mean, V):
+    """Squared Frobenius norm of what the basis V leaves out of X - mean."""
+    Xc = np.asarray(X, dtype=np.float64) - mean
+    R = Xc - (Xc @ V.T) @ V
+    return float(np.sum(R * R))
+
+
+def adamw_step(p, g, m, v, t, lr, weight_decay, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One AdamW update of the parameters p with gradient g at step t >= 1;
+    m, v are the moment estimates before the step.  Returns (p, m, v)."""
+    p, g = np.asarray(p, np.float64), np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    p = p - lr * (m_hat / (np.sqrt(v_hat) + eps) + weight_decay * p)
+    return p, m, v
+
+
+def ridge_head(h, y, ridge):
+    """Coefficients [h.shape[1] + 1] (weights, then the constant) minimising
+    ||[h 1] w - y||^2 + ridge * n * ||w||^2, solved as the ordinary least
+    squares problem of the stacked system [[h 1]; sqrt(ridge n) I] w = [y; 0]
+    (numpy.linalg.lstsq)."""
+    h = np.asarray(h, np.float64)
+    y = np.asarray(y, np.float64)
+    n, k = h.shape
+    X = np.concatenate([h, np.ones((n, 1))], axis=1)
+    A = np.concatenate([X, math.sqrt(ridge * n) * np.eye(k + 1)], axis=0)
+    rhs = np.concatenate([y, np.zeros(k + 1)])
+    return np.linalg.lstsq(A, rhs, rcond=None)[0]
+
+
+def predicted_log10_mismatch(weights, x, head):
+    """Head output for normalised inputs x [B][4]: the last hidden layer as
+    the GPU stores it (bf16 of silu(z3)) times head[:-1], plus head[-1]."""
+    _, cache = mlp_forward(weights, x, emulate_bf16=True)
+    h3 = cache[-1][0]          # the output layer's (rounded) input
+    return h3 @ np.asarray(head[:-1], np.float64) + float(head[-1])
+
+
+def keeps_surrogate(logmm, threshold):
+    """Routing: surrogate where the prediction is <= threshold (NaN falls back)."""
+    return np.asarray(logmm) <= threshold

@@ -39,7 +39,8 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_ragged_offsets", "gw_generate_ragged", "gw_ragged_graph_create",
            "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune",
            "gw_run_psd_workspace_size", "gw_run_psd", "gw_whiten_filter", "gw_generate_batch_runpsd",
-           "gw_generate_batch_pairs", "gw_generate_batch_oversampled")
+           "gw_generate_batch_pairs", "gw_generate_batch_oversampled", "gw_surrogate_set_adam",
+           "gw_surrogate_get_state")
 
 TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH, RTUNE_WINDOW_MODE = 1, 2, 3, 4, 5
@@ -109,6 +110,8 @@ def lib():
             "gw_surrogate_save": ([vp, ctypes.c_char_p], i32),
             "gw_surrogate_load": ([vp, ctypes.c_char_p], i32),
             "gw_surrogate_set_state": ([vp, vp, vp, vp, vp, vp, vp], i32),
+            "gw_surrogate_get_state": ([vp, vp, vp, vp, vp, vp, vp], i32),
+            "gw_surrogate_set_adam": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
             "gw_workspace_size_surrogate": ([vp, i64, ctypes.POINTER(i64)], i32),
             "gw_generate_batch_surrogate": ([vp, vp, u64, u64, i64, vp, i64, vp, vp, vp, ctypes.c_float, vp,
                                              i64, vp], i32),

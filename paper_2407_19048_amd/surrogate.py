@@ -89,6 +89,18 @@ class Surrogate:
                 raise ValueError("state array shape %s, expected %s" % (a.shape, sh))
         self._check(lib().gw_surrogate_set_state(self._h, *[a.ctypes.data for a in arrs]), "set_state")
 
+    def get_state(self):
+        """(basis, mean, A, zmean, zstd, head) as host arrays."""
+        arrs = [np.empty((2, 64, NODES), np.float32), np.empty((2, NODES), np.float64),
+                np.empty((N_FEAT, N_OUT), np.float32), np.empty(N_OUT, np.float32), np.empty(N_OUT, np.float32),
+                np.empty(HIDDEN + 1, np.float32)]
+        self._check(lib().gw_surrogate_get_state(self._h, *[a.ctypes.data for a in arrs]), "get_state")
+        return tuple(arrs)
+
+    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib().gw_surrogate_set_adam(self._h, ctypes.c_double(beta1), ctypes.c_double(beta2),
+                                                ctypes.c_double(eps)), "set_adam")
+
     def save(self, path):
         self._check(lib().gw_surrogate_save(self._h, path.encode()), "save")
 
@@ -150,7 +162,7 @@ class Surrogate:
         return params
 
     def fit(self, seed=3, n_basis=32768, n_train=1 << 20, epochs=20, batch=8192, lr=2e-3, lr_min=2e-5,
-            n_head=8192, psd=None, log=None, init_seed=17):
+            weight_decay=1e-2, n_head=8192, psd=None, log=None, init_seed=17):
         """Build the basis and skip path, train the MLP and fit the head."""
         import torch
         t0 = time.perf_counter()
@@ -187,6 +199,12 @@ class Surrogate:
         steps_per_epoch = n_train // batch
         total = steps_per_epoch * epochs
         loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        # loss of the initial network on the first batch (gradients only, no update)
+        grads = torch.empty(self.n_weights, dtype=torch.float32, device=dev)
+        self.gradients(theta[:batch], Z[:batch], grads, loss)
+        torch.cuda.synchronize()
+        initial_mse = float(loss.item()) / (batch * N_OUT)
+        del grads
         step = 0
         for ep in range(epochs):
             shift = (ep * 7919 * batch // 13) % n_train
@@ -194,7 +212,7 @@ class Surrogate:
                 i0 = (shift + j * batch) % (n_train - batch + 1)
                 a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / total))
                 want = (j == steps_per_epoch - 1)
-                self.train_step(theta[i0:i0 + batch], Z[i0:i0 + batch], a, 0.0, loss if want else None)
+                self.train_step(theta[i0:i0 + batch], Z[i0:i0 + batch], a, weight_decay, loss if want else None)
                 step += 1
             torch.cuda.synchronize()
             mse = float(loss.item()) / (batch * N_OUT)
@@ -207,8 +225,8 @@ class Surrogate:
         head_stats = None
         if psd is not None and n_head > 0:
             head_stats = self.fit_mismatch_head(seed + 1, n_head, psd)
-        return dict(seconds_data=t_data, seconds_train=t_train, steps=total, final_mse=self.history[-1],
-                    head=head_stats)
+        return dict(seconds_data=t_data, seconds_train=t_train, steps=total, initial_mse=initial_mse,
+                    final_mse=self.history[-1], weight_decay=weight_decay, head=head_stats)
 
     def mismatch_vs_plain(self, params, psd):
         """(mm float64 [B], predicted log10 mm float32 [B]) against the plain model."""
@@ -232,14 +250,24 @@ class Surrogate:
         import torch
         p = self._draw(seed, 1 << 40, n)
         mm, _ = self.mismatch_vs_plain(p, psd)
-        y = torch.log10(torch.clamp(mm, min=1e-12)).float().cpu().numpy()
         theta = p[:4].t().float().contiguous()
         h3 = torch.empty((n, HIDDEN), dtype=torch.float32, device="cuda")
         for i0 in range(0, n, self.max_batch):
             m = min(self.max_batch, n - i0)
             self.hidden(theta[i0:i0 + m], h3[i0:i0 + m])
+        self.fit_head(h3, mm.cpu().numpy(), 1e-4)
+        mm = mm.cpu().numpy()
+        return dict(n=n, median_mm=float(np.median(mm)), p90_mm=float(np.percentile(mm, 90)))
+
+    def fit_head(self, h3, mm, ridge):
+        """Ridge fit of the log10-mismatch head (see gw_surrogate_fit_head);
+        h3 device float [n][256], mm host mismatches [n]."""
+        import torch
+        n = h3.shape[0]
+        _want(h3, torch.float32, (n, HIDDEN), "h3")
+        mm = np.ascontiguousarray(mm, dtype=np.float64)
+        if mm.shape != (n,):
+            raise ValueError("mm must have shape (%d,)" % n)
         torch.cuda.synchronize()
-        y = np.ascontiguousarray(y)
-        self._check(lib().gw_surrogate_fit_head(self._h, _ptr(h3), y.ctypes.data, n, ctypes.c_double(1e-4)),
+        self._check(lib().gw_surrogate_fit_head(self._h, _ptr(h3), mm.ctypes.data, n, ctypes.c_double(ridge)),
                     "fit_head")
-        return dict(n=n, median_mm=float(np.median(10 ** y)), p90_mm=float(np.percentile(10 ** y, 90)))
