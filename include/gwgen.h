@@ -216,6 +216,22 @@ gw_status gw_generate_batch(gw_ctx* ctx, uint64_t seed, uint64_t batch_index,
                             void* workspace, int64_t workspace_bytes,
                             hipStream_t stream);
 
+/* gw_generate_batch_noalloc -- gw_generate_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results except the
+ * workspace: the call uses the library's static device scratch area of
+ * GW_SCRATCH_BYTES on the device the context was created on, held until the
+ * process ends, and calls no allocator.  B must satisfy
+ * gw_workspace_size(B) <= GW_SCRATCH_BYTES (B <= 2600 at 3 detectors with
+ * L = 4096), else GW_EINVAL.  Every call on a device shares that device's
+ * area, which keeps the last call's contents: calls that overlap in time on
+ * one device (other streams or host threads) race, so serialise them; the
+ * parameters and offsets are not readable by the caller (use params_f32). */
+#define GW_SCRATCH_BYTES (64ll << 20)
+gw_status gw_generate_batch_noalloc(gw_ctx* ctx, uint64_t seed, uint64_t batch_index, int64_t B,
+                                    const float* bg, int64_t L_bg, float* out, float* params_f32,
+                                    uint32_t* status, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Per-run PSD mode (section 3.2 fits one noise spectrum to the background
  * chunk held on the accelerator): one Welch PSD per detector for the run,

@@ -22,6 +22,8 @@ struct gw_ctx {
   // exp(-2 pi i k / N) (cpx<float>[N/2]) for k < N/2, stored at the position
   // (k mod N2) N1 + k / N2 of bin k in the transposed four-step spectrum
   void* long_tabs = nullptr;
+  int device = 0;             // HIP device the context was created on
+  void* scratch = nullptr;    // that device's copy of the library's static scratch area
   std::string err;
 };
 

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -590,7 +591,37 @@ namespace gw {
 gw_status validate_config(const gw_config* g, DevCfg* dc, std::string* why) { return validate_cfg(g, dc, why); }
 }  // namespace gw
 
+// Static scratch area of the allocation-free batch entry point: one copy per
+// device, held until the process ends.  Its name is only a host-side stand-in
+// in host code; the device address of each device's copy is resolved once,
+// with that device current (resolve_scratch), and used from then on.
+static __device__ __align__(256) unsigned char scratch[GW_SCRATCH_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxScratchDevices = 256;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch area (resolved on first use).
+gw_status resolve_scratch(int dev, void** addr, std::string* why) {
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    *why = "device index out of range for the scratch table";
+    return GW_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return GW_EHIP;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *addr = g_scratch_addr[dev];
+  return GW_OK;
+}
 
 static int64_t ws_params_bytes(int64_t B) { return ((B * 12 * 8 + 255) / 256) * 256; }
 static int64_t ws_offset_bytes(int64_t B) { return ((B * 8 + 255) / 256) * 256; }
@@ -811,6 +842,15 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
   gw_ctx* c = new gw_ctx();
   c->cfg = *cfg;
   c->dc = dc;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    gw_destroy(c);
+    return GW_EHIP;
+  }
+  s = resolve_scratch(c->device, &c->scratch, &c->err);
+  if (s != GW_OK) {
+    gw_destroy(c);
+    return s;
+  }
   std::vector<double> hc(dc.F), hl(dc.F), h53(dc.F);
   for (int k = 0; k < dc.F; ++k) {
     hc[k] = std::cbrt(double(k));
@@ -1045,6 +1085,23 @@ gw_status gw_generate_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, int6
   if (batch_index > (UINT64_MAX - uint64_t(B)) / uint64_t(B)) return fail(c, GW_EINVAL, "batch_index overflows");
   return enqueue_batch(c, seed, batch_index, nullptr, B, bg, L_bg, out, params_f32, status, workspace, kStageAll,
                        stream);
+}
+
+gw_status gw_generate_batch_noalloc(gw_ctx* c, uint64_t seed, uint64_t batch_index, int64_t B, const float* bg,
+                                    int64_t L_bg, float* out, float* params_f32, uint32_t* status,
+                                    hipStream_t stream) {
+  GW_CHECK_CTX(c);
+  if (B < 0) return fail(c, GW_EINVAL, "bad B");
+  int64_t need = 0;
+  gw_workspace_size(c, B, &need);
+  if (need > GW_SCRATCH_BYTES)
+    return fail(c, GW_EINVAL, "batch too large for the static scratch area (needs " + std::to_string(need) +
+                                  " bytes, the area holds " + std::to_string(int64_t(GW_SCRATCH_BYTES)) + ")");
+  if (!c->scratch) return fail(c, GW_EHIP, "scratch area not resolved");
+  // nothing in the area must start at zero: the prior kernel writes the
+  // parameters, offsets, status and per-sample constants, Welch every PSD bin
+  return gw_generate_batch(c, seed, batch_index, B, bg, L_bg, out, params_f32, status, c->scratch,
+                           GW_SCRATCH_BYTES, stream);
 }
 
 gw_status gw_graph_create(gw_ctx* c, uint64_t seed, uint64_t first_batch, int64_t B, const float* bg, int64_t L_bg,

@@ -18,6 +18,7 @@ STATUS_NONPOSITIVE_PSD = 2
 STATUS_NONFINITE_DATA = 4
 STATUS_CUT_AT_NYQUIST = 8
 STATUS_SURROGATE_FALLBACK = 16
+SCRATCH_BYTES = 64 << 20   # GW_SCRATCH_BYTES
 N_PARAMS = 12
 (Q_N, Q_F, Q_P, Q_L, Q_K, Q_FW, Q_NDET, Q_NPARAMS) = range(8)
 
@@ -40,7 +41,7 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_ragged_set_tuning", "gw_ragged_get_tuning", "gw_ragged_autotune",
            "gw_run_psd_workspace_size", "gw_run_psd", "gw_whiten_filter", "gw_generate_batch_runpsd",
            "gw_generate_batch_pairs", "gw_generate_batch_oversampled", "gw_surrogate_set_adam",
-           "gw_surrogate_get_state")
+           "gw_surrogate_get_state", "gw_generate_batch_noalloc")
 
 TUNE_ORD_WINDOW, TUNE_ORD_WELCH, TUNE_OCC_WELCH = 1, 2, 3
 RTUNE_ORD_WINDOW, RTUNE_ORD_WELCH, RTUNE_GRID_WINDOW, RTUNE_GRID_WELCH, RTUNE_WINDOW_MODE = 1, 2, 3, 4, 5
@@ -87,6 +88,7 @@ def lib():
             "welch_psd": ([vp, vp, i64, vp, i64, vp, vp], i32),
             "whiten": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "gw_generate_batch": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp, i64, vp], i32),
+            "gw_generate_batch_noalloc": ([vp, u64, u64, i64, vp, i64, vp, vp, vp, vp], i32),
             "gw_surrogate_create": ([vp, i64, ctypes.POINTER(vp)], i32),
             "gw_surrogate_destroy": ([vp], i32),
             "gw_surrogate_last_error": ([vp], ctypes.c_char_p),
@@ -306,6 +308,19 @@ class Generator:
                                             bg.shape[1], _ptr(out), _ptr(params_f32), _ptr(status),
                                             _ptr(workspace), nbytes, _stream()),
                     "gw_generate_batch")
+
+    def generate_batch_noalloc(self, seed, batch_index, B, bg, out, params_f32=None, status=None):
+        """gw_generate_batch on the library's static scratch area (no workspace)."""
+        import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
+        _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
+        if params_f32 is not None:
+            _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
+        if status is not None:
+            _want(status, torch.int32, (B,), "status")
+        self._check(lib().gw_generate_batch_noalloc(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
+                                                    bg.shape[1], _ptr(out), _ptr(params_f32), _ptr(status),
+                                                    _stream()), "gw_generate_batch_noalloc")
 
     def mismatch(self, ha, hb, psd, params, mm):
         """Noise-weighted mismatch per sample (see gw_mismatch)."""

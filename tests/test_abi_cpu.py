@@ -90,4 +90,5 @@ def test_null_context_rejected():
     assert L.welch_psd(null, null, 1 << 20, null, 4, null, null) == gwgen.GW_EINVAL
     assert L.whiten(null, null, null, 4, null, null, null) == gwgen.GW_EINVAL
     assert L.gw_generate_batch(null, 1, 0, 4, null, 1 << 20, null, null, null, null, 0, null) == gwgen.GW_EINVAL
+    assert L.gw_generate_batch_noalloc(null, 1, 0, 4, null, 1 << 20, null, null, null, null) == gwgen.GW_EINVAL
     assert L.gw_destroy(null) == gwgen.GW_OK
