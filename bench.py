@@ -53,9 +53,30 @@ def _oracle_worker(args):
                 return done, time.perf_counter() - t0
 
 
-def cpu_baseline(cfg, bg, seed, B, budget_s, workers):
-    """The FP64 oracle on the same workload: `workers` processes, each
-    regenerating its share of a fixed sample set until the time budget."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """(cores this process may run on, cores the host reports)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return usable, os.cpu_count() or usable
+
+
+def cpu_baseline(cfg, bg, seed, B, budget_s, workers, one_core_s):
+    """The FP64 oracle on the same workload: `workers` single-threaded
+    processes, each regenerating its share of a fixed sample set until the
+    time budget; then one process alone for the one-core figure."""
     import numpy as np
     import oracle
     z = oracle.derived_sizes(cfg)
@@ -70,13 +91,18 @@ def cpu_baseline(cfg, bg, seed, B, budget_s, workers):
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
         res = pool.map(_oracle_worker, jobs)
+        one = pool.apply(_oracle_worker, ((cfg, slices[:4], [params[:, i] for i in range(4)], one_core_s),))
     wall = time.perf_counter() - t0
     done = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
+    usable, reported = host_cores()
     return dict(value=done / busy, unit="samples/s", cores=workers, kind="oracle",
+                one_core=round(one[0] / one[1], 2), host_cores_usable=usable, host_cores_reported=reported,
+                cpu_model=cpu_model(),
                 sample="%d oracle samples (FP64 NumPy, %d distinct draws of the paper-scale "
-                       "workload) over %.1f s in %d processes, one thread each; %.1f s wall "
-                       "with start-up" % (done, n_distinct, busy, workers, wall))
+                       "workload) over %.1f s in %d processes, one thread each, then %d samples "
+                       "in one process alone over %.1f s; %.1f s wall with start-up"
+                       % (done, n_distinct, busy, workers, one[0], one[1], wall))
 
 
 # --------------------------------------------------------- surrogate leg
@@ -95,16 +121,27 @@ def surrogate_leg(gen, bg, args, K, W, dev):
     psd = torch.from_numpy(inputs.true_psd(f, gen.cfg["fs"]).astype(np.float32)).to(dev)
     t0 = time.perf_counter()
     s = GS.Surrogate(gen, max_batch=8192)
-    fit = s.fit(seed=3, n_basis=16384, n_train=1 << 19, epochs=40, batch=8192, lr=2e-3, n_head=8192, psd=psd)
+    n_train, n_basis = 1 << 20, 32768
+    fit = s.fit(seed=3, n_basis=n_basis, n_train=n_train, epochs=40, batch=8192, lr=2e-3, weight_decay=1e-2,
+                n_head=8192, psd=psd)
     t_fit = time.perf_counter() - t0
-    log("surrogate trained in %.1f s (final mse %.3f)" % (t_fit, fit["final_mse"]))
+    log("surrogate trained in %.1f s (mse %.3f -> %.3f)" % (t_fit, fit["initial_mse"], fit["final_mse"]))
     # held-out mismatch
     p = torch.empty((12, 8192), dtype=torch.float64, device=dev)
     o = torch.empty(8192, dtype=torch.int64, device=dev)
     gen.sample_params(4, 1 << 41, 8192, z["P"] + z["N"], p, o)
     mm, logmm = s.mismatch_vs_plain(p, psd)
     mm = mm.cpu().numpy()
-    fb = (logmm.cpu().numpy() > -3.0)
+    fb = ~(logmm.cpu().numpy() <= -3.0)
+    # what the network adds: the same state with its output layer zeroed
+    # (coefficients from the linear skip path alone)
+    s_lin = GS.Surrogate(gen, max_batch=8192)
+    s_lin.set_state(*s.get_state())
+    flat = s.get_weights()
+    flat[sum(a * b + b for a, b in GS.LAYERS[:-1]):] = 0.0
+    s_lin.set_weights(flat)
+    mm_lin = s_lin.mismatch_vs_plain(p, psd)[0].cpu().numpy()
+    s_lin.close()
     # waveform stage alone, same draws
     hp = torch.empty((8192, z["F"]), dtype=torch.complex64, device=dev)
     hc = torch.empty_like(hp)
@@ -158,7 +195,10 @@ def surrogate_leg(gen, bg, args, K, W, dev):
         "waveform_stage_ms": {"plain": round(wf_plain, 4), "surrogate": round(wf_surr, 4),
                               "gain": round(wf_plain / wf_surr, 3)},
         "mismatch_heldout": {"n": 8192, "median": float(np.median(mm)), "p90": float(np.percentile(mm, 90)),
-                             "median_after_fallback": float(np.median(np.where(fb, 0.0, mm)))},
+                             "median_after_fallback": float(np.median(np.where(fb, 0.0, mm))),
+                             "median_skip_path_only": float(np.median(mm_lin))},
+        "training": {"n_train": n_train, "n_basis": n_basis, "weight_decay": fit["weight_decay"],
+                     "initial_mse": round(fit["initial_mse"], 4), "final_mse": round(fit["final_mse"], 4)},
         "fallback_rate": round(fallback_rate, 4),
         "train_seconds": round(t_fit, 2),
         "train_steps": fit["steps"],
@@ -390,6 +430,8 @@ def main():
     ap.add_argument("--log2-bg", type=int, default=27)
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="oracle processes of the CPU baseline (at most the usable cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-batch", type=int, default=8192)
@@ -421,9 +463,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        workers = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(cfg, bg_np, 2, B, args.cpu_budget, workers)
-        log("cpu baseline: %.1f samples/s on %d cores" % (cpu["value"], cpu["cores"]))
+        # every core this process may use, up to the host's share per GPU
+        # (16 on the GPU hosts this runs on)
+        workers = max(1, min(args.cpu_workers, host_cores()[0]))
+        cpu = cpu_baseline(cfg, bg_np, 2, B, args.cpu_budget, workers, args.cpu_budget / 2)
+        log("cpu baseline: %.1f samples/s on %d cores (%.1f on one core; %s, %d usable of %d reported)"
+            % (cpu["value"], cpu["cores"], cpu["one_core"], cpu["cpu_model"], cpu["host_cores_usable"],
+               cpu["host_cores_reported"]))
 
     import torch
     from paper_2407_19048_amd import gwgen
@@ -494,15 +540,23 @@ def main():
     from paper_2407_19048_amd.profiling import measured_traffic
     traffic = measured_traffic("k_welch", "paper_scale_B%d" % B)
 
-    if args.copy_probe_gib > 0:
-        n = int(args.copy_probe_gib * (1 << 30)) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: 3 x %d bytes read + written" % (4 * n))
-        del src, dst
+    # device-to-device copy of 1 GiB (or --copy-probe-gib): the bandwidth a
+    # plain streaming kernel reaches on this part, timed with events on the
+    # current stream, and the known transfer that calibrates byte counters
+    gib = args.copy_probe_gib if args.copy_probe_gib > 0 else 1.0
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * n / (ev0.elapsed_time(ev1) / 5 * 1e-3) / 1e9
+    log("copy probe: %d bytes read + written per copy, %.0f GB/s" % (4 * n, copy_gbs))
+    del src, dst
 
     # whole step, algorithmic bytes per sample: D (P + N) reads + D N writes
     step_bytes = B * n_det * ((z["P"] + z["N"]) + z["N"]) * 4
@@ -569,6 +623,10 @@ def main():
             "ms_per_launch": round(welch_ms, 4),
             "hbm_achieved_gbs": round(welch_gbs, 1),
             "hbm_frac": round(welch_gbs / HBM_PEAK_GBS, 4),
+            "copy_gbs": round(copy_gbs, 1),
+            "hbm_frac_of_copy": round(welch_gbs / copy_gbs, 4),
+            "step_achieved_gbs": round(step_gbs, 1),
+            "step_frac_of_copy": round(step_gbs / copy_gbs, 4),
             "bytes_per_launch": welch_bytes,
             "traffic": traffic,
         },

@@ -1,4 +1,13 @@
-"""HBM traffic of a kernel from two rocprofv3 counter runs.
+"""Summaries of rocprofv3 runs for the profiles/ folder.
+
+    python -m paper_2407_19048_amd.profiling stats STATS_CSV TITLE "COMMAND"
+        kernel time table (markdown) from a --kernel-trace --stats run
+    python -m paper_2407_19048_amd.profiling counters COUNTER_DIR KERNEL_SUBSTR TITLE "COMMAND"
+        per-dispatch means of every counter of a --pmc run for the matching kernels (markdown)
+    python -m paper_2407_19048_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL VARIANT GRID WORKLOAD COPY_GIB "COMMAND"
+        HBM traffic record (JSON in profiles/) as described below
+
+HBM traffic of a kernel from two rocprofv3 counter runs.
 
 FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are taken in separate runs of
 the same command, which also copies a device buffer of known size (bench.py
@@ -6,8 +15,6 @@ the same command, which also copies a device buffer of known size (bench.py
 the known size on that copy, so the result is in bytes moved between the
 chip and HBM.  The summary is stored with a hash of the kernel sources; the
 benchmark reports it only while the hash still matches.
-
-    python -m paper_2407_19048_amd.profiling FETCH_DIR WRITE_DIR KERNEL VARIANT GRID WORKLOAD COPY_GIB "COMMAND"
 
 VARIANT is a substring of the demangled kernel name that selects the
 instantiation the benchmark times (other variants, e.g. the autotuner's
@@ -106,8 +113,61 @@ def summarise(fetch_dir, write_dir, kernel, variant, grid, workload, copy_gib, c
     return rec
 
 
+def _col(header, *names):
+    low = {h.lower(): h for h in header}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    raise KeyError("none of %s in %s" % (names, header))
+
+
+def stats_table(stats_csv, title, command, top=14):
+    """Markdown table of the kernels of a rocprofv3 --stats run, by total time."""
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    if not rows:
+        raise ValueError("empty stats file %s" % stats_csv)
+    h = list(rows[0].keys())
+    name, calls = _col(h, "Name", "KernelName"), _col(h, "Calls")
+    total, avg = _col(h, "TotalDurationNs", "TotalDuration"), _col(h, "AverageNs", "Average")
+    rows.sort(key=lambda r: -float(r[total]))
+    grand = sum(float(r[total]) for r in rows)
+    out = ["# %s" % title, "", "Command (one MI355X):", "", "    %s" % command, "",
+           "Source: `%s` (every dispatch of the run)." % os.path.basename(stats_csv), "",
+           "| kernel | calls | average | total | share |", "|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append("| `%s` | %s | %.4f ms | %.3f ms | %.2f %% |"
+                   % (r[name], r[calls], float(r[avg]) / 1e6, float(r[total]) / 1e6, 100.0 * float(r[total]) / grand))
+    return "\n".join(out) + "\n"
+
+
+def counters_table(counter_dir, kernel_substr, title, command):
+    """Markdown table: per-dispatch mean of each counter for the kernels whose
+    name contains kernel_substr (one line per kernel name and grid)."""
+    rows = [r for r in _rows(counter_dir) if kernel_substr in r["Kernel_Name"]]
+    if not rows:
+        raise ValueError("no dispatch of %s in %s" % (kernel_substr, counter_dir))
+    acc = {}
+    for r in rows:
+        key = (r["Kernel_Name"], int(r["Grid_Size"]))
+        acc.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for v in acc.values() for c in v})
+    out = ["# %s" % title, "", "Command (one MI355X):", "", "    %s" % command, "",
+           "Per-dispatch means (dispatch count in brackets).", "",
+           "| kernel | grid | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for (k, g), v in sorted(acc.items()):
+        cells = ["%.4g (%d)" % (sum(v[c]) / len(v[c]), len(v[c])) if c in v else "" for c in names]
+        out.append("| `%s` | %d | %s |" % (k, g, " | ".join(cells)))
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
-    if len(a) != 8:
+    if len(a) == 4 and a[0] == "stats":
+        sys.stdout.write(stats_table(a[1], a[2], a[3]))
+    elif len(a) == 5 and a[0] == "counters":
+        sys.stdout.write(counters_table(a[1], a[2], a[3], a[4]))
+    elif len(a) == 9 and a[0] == "traffic":
+        print(json.dumps(summarise(a[1], a[2], a[3], a[4], int(a[5]), a[6], float(a[7]), a[8]), indent=1))
+    else:
         sys.exit(__doc__)
-    print(json.dumps(summarise(a[0], a[1], a[2], a[3], int(a[4]), a[5], float(a[6]), a[7]), indent=1))
