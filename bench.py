@@ -122,7 +122,7 @@ def surrogate_leg(gen, bg, args, K, W, dev):
     t0 = time.perf_counter()
     s = GS.Surrogate(gen, max_batch=8192)
     n_train, n_basis = 1 << 20, 32768
-    fit = s.fit(seed=3, n_basis=n_basis, n_train=n_train, epochs=40, batch=8192, lr=2e-3, weight_decay=1e-2,
+    fit = s.fit(seed=3, n_basis=n_basis, n_train=n_train, epochs=40, batch=8192, lr=2e-3, weight_decay=2e-3,
                 n_head=8192, psd=psd)
     t_fit = time.perf_counter() - t0
     log("surrogate trained in %.1f s (mse %.3f -> %.3f)" % (t_fit, fit["initial_mse"], fit["final_mse"]))

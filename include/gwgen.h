@@ -281,7 +281,7 @@ gw_status gw_generate_batch_pairs(gw_ctx* ctx, uint64_t seed, uint64_t batch_ind
                                   float* params_f32, uint32_t* status, void* workspace,
                                   int64_t workspace_bytes, hipStream_t stream);
 /* gw_generate_batch with ext_k sky positions per intrinsic draw (the
- * augmentation in the extrinsic parameters proposed in section 5): global
+ * augmentation in the extrinsic parameters proposed in section 6): global
  * sample g is sky position g % ext_k of intrinsic draw g / ext_k.  Every
  * parameter row is drawn at Philox index g / ext_k; alpha, delta, psi and
  * the background offset use the Philox sub-counter g % ext_k (the fourth

@@ -207,9 +207,14 @@ __device__ __forceinline__ cpx<T> signal_bin(const DevCfg& cf, const WinArgs& a,
 // Projected signal at window bin k from surrogate node values: binary64
 // Newtonian phase + interpolated phase residual (revolutions), amplitude
 // A_N(f_k) times the interpolated ratio.
+// Node values staged in LDS: typed as such, so that their gathers compile to
+// LDS reads rather than generic (flat) loads, which would also wait for the
+// global loads issued ahead.
+typedef const __attribute__((address_space(3))) float* lds_cfptr;
+
 template <class T>
 __device__ __forceinline__ cpx<T> signal_bin_surr(const DevCfg& cf, const WinArgs& a, const WfScalars& w,
-                                                  const float* nd, T cpl, T cxx, double tauT, int k) {
+                                                  lds_cfptr nd, T cpl, T cxx, double tauT, int k) {
   if (k <= 0 || k < cf.kmin || k >= w.kend) return {T(0), T(0)};
   const double lk3 = a.lnk3[k], k53 = a.k53[k];
   // u = (ln(Ms k / T) - ln Mf_lo) / dlog, ln(Ms/T) = 3 ln v1 - ln pi
@@ -249,12 +254,11 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   static_assert(SRC >= 0 && SRC <= 4, "source");
   PowTwiddle<T, NC, ORD> tw{twtab};
   if constexpr (SRC == 3) {
-    // the sample's node values go to LDS once; the barriers of the forward
-    // transform below make them visible to the whole (sub-)block
-    if (snodes) {
-      const float* src = a.nodes + b * 2 * kSurrNodes;
-      for (int i = t; i < 2 * kSurrNodes; i += NT) snodes[i] = src[i];
-    }
+    // the sample's node values go to LDS once (snodes: 2 x 1024 floats of
+    // LDS); the barriers of the forward transform below make them visible to
+    // the whole (sub-)block
+    const float* src = a.nodes + b * 2 * kSurrNodes;
+    for (int i = t; i < 2 * kSurrNodes; i += NT) snodes[i] = src[i];
   }
   cpx<T> v[16];
   uint32_t flag = 0;
@@ -281,12 +285,11 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
   WfScalars wsh;
   if constexpr (SRC == 1 || SRC == 3 || SRC == 4) wsh = load_const(a.wf + b);
   bool use_surr = false;
-  const float* nd = nullptr;
+  lds_cfptr nd = nullptr;
   if constexpr (SRC == 3) {
     // a NaN prediction fails the test and falls back to the plain model
     use_surr = load_const(a.logmm + b) <= a.logmm_max;
-    nd = a.nodes + b * 2 * kSurrNodes;
-    if (snodes) nd = snodes;  // staged before the forward transform
+    nd = (lds_cfptr)snodes;  // staged before the forward transform
     if (active && !use_surr && t == 0 && d == 0 && a.status)
       atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
   }
