@@ -321,10 +321,13 @@ gw_status gw_graph_destroy(gw_graph* graph);
  * 1 puts it first (same result up to rounding; which is faster depends on
  * the size).  GW_TUNE_OCC_WELCH: 2 or 3 waves per SIMD for the Welch kernel
  * (3 caps it at 168 VGPRs, which the binary32 kernels meet without spills
- * at L = 4096).  Binary64 kernels (precision 2) have one variant.  Defaults
- * (before gw_autotune): OCC_WELCH 3 for binary32 transforms of L = 4096,
- * else 2; ORD_WINDOW 1 for N = 16384 with binary32 transforms, else 0;
- * ORD_WELCH 0. */
+ * at L = 4096).  Binary64 kernels (precision 2) have one variant.  For
+ * windows longer than 2^15 samples GW_TUNE_ORD_WINDOW selects the structure
+ * of the four-step window stage instead: 1 fuses the row transforms, the
+ * bins and the inverse row transforms into one pass per row pair, 0 runs
+ * them as three passes.  Defaults (before gw_autotune): OCC_WELCH 3 for
+ * binary32 transforms of L = 4096, else 2; ORD_WINDOW 1 for N = 16384 or
+ * N > 32768 with binary32 transforms, else 0; ORD_WELCH 0. */
 #define GW_TUNE_ORD_WINDOW 1
 #define GW_TUNE_ORD_WELCH  2
 #define GW_TUNE_OCC_WELCH  3

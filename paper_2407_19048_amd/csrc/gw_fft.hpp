@@ -36,6 +36,21 @@ template <int DIR, class T> __device__ __forceinline__ cpx<T> twmul(cpx<T> a, cp
   else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
 }
 
+// Returns p unchanged, but the compiler can no longer prove two loads through
+// it the same: table loads stay next to the transform that uses them instead
+// of being shared with (and kept live across) other transforms of the same
+// kernel or loop iterations.  p points to global memory and is laundered as a
+// global pointer, so that loads through it remain global loads: through a
+// generic pointer they would become flat loads, which also count against the
+// LDS wait counter and make every LDS barrier wait for them.
+template <class T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  typedef const __attribute__((address_space(1))) T* gptr;
+  gptr g = (gptr)p;
+  asm volatile("" : "+s"(g));
+  return (const T*)g;
+}
+
 // Workgroup barrier for the LDS exchanges: waits only for this wave's LDS
 // operations (lgkmcnt) before s_barrier.  __syncthreads() also waits for
 // every outstanding global load, which would expose the latency of loads

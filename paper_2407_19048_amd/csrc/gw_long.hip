@@ -278,6 +278,212 @@ __global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
   if (threadIdx.x == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
 }
 
+// One pair of packed-spectrum bins (k, km = NC - k), k <= NC/2: A = Z[k] and
+// Bm = Z[km] in; out, the packed spectrum of the whitened window (SRC 1 with
+// the in-register signal added) at the same two bins.  pk, pm: positions of k
+// and km in the transposed bin tables.
+template <class TP, int SRC>
+__device__ __forceinline__ void long_pair(const LongArgs& a, const WfScalars& wsh, float cpl, float cxx, double tauT,
+                                          const float* psd, int k, int64_t pk, int64_t pm, cpx<float>& A,
+                                          cpx<float>& Bm, uint32_t& flag) {
+  const DevCfg& cf = a.w.cf;
+  const int NC = a.NC, km = NC - k;
+  const cpx<float> W = a.twr_t[pk];  // exp(-2 pi i k / N)
+  const cpx<float> s = cadd(A, cconj(Bm));
+  const cpx<float> u = cmul(W, csub(A, cconj(Bm)));
+  cpx<float> Xk = {0.5f * (s.x + u.y), 0.5f * (s.y - u.x)};
+  cpx<float> Xm = {0.5f * (s.x - u.y), 0.5f * (-s.y - u.x)};
+  if constexpr (SRC == 1) {
+    Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, k, a.kc_t[pk], a.lk_t[pk]));
+    if (km != k) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, a.kc_t[pm], a.lk_t[pm]));
+  }
+  const int ia = psd_index(cf, k, NC), ib = psd_index(cf, km, NC);
+  const cpx<float> Yk = cscale(Xk, whiten_gain_at<float>(cf, psd[ia], psd[ia + 1], k, NC, flag));
+  cpx<float> Ym = cscale(Xm, whiten_gain_at<float>(cf, psd[ib], psd[ib + 1], km, NC, flag));
+  if (km == k) Ym = Yk;
+  const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
+  const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W);
+  A = {p.x - q.y, p.y + q.x};
+  Bm = {p.x + q.y, -p.y + q.x};
+}
+
+// p (uniform over the workgroup) unchanged, but addresses derived from it are
+// not shared with (and kept live across) other phases of the kernel that use
+// the same pointer.
+template <class T>
+__device__ __forceinline__ T* fresh(T* p) {
+  typedef __attribute__((address_space(1))) T* gptr;
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  // readfirstlane works on (signed) int: widen its result as unsigned, or a
+  // low word with the top bit set would sign-extend into the high word
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u))));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u >> 32))));
+  const uint64_t s = uint64_t(lo) | (uint64_t(hi) << 32);
+  gptr g = (gptr)reinterpret_cast<T*>(s);
+  asm volatile("" : "+s"(g));
+  return (T*)g;
+}
+
+// The lane index t, unchanged, as a value the compiler cannot prove equal to
+// t elsewhere: index and LDS-address arithmetic of one phase is then not
+// shared with (and kept live across) the other phases.
+__device__ __forceinline__ int fresh_lane(int t) {
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Rows, bins and inverse rows of one row pair in one workgroup (replacing
+// three passes through HBM).  Bin k = r + N2 c sits at row r, column c of the
+// transposed spectrum, and its partner NC - k at row N2 - r, column N1 - 1 - c
+// (row 0 and row N2/2 pair with themselves: columns N1 - c and N1 - 1 - c).
+// Grid: B*D*(N2/2 + 1) workgroups of N1/16 threads; workgroup (item, r) owns
+// rows r and N2 - r.  Two-row pairs: the spectrum of row r goes back to its
+// row of the buffer; thread t writes, and later reads back, exactly the
+// columns t + NT j (the output layout of the transform covers them), so the
+// round trip needs no barrier and holds no registers while row N2 - r is
+// transformed and stored to LDS in natural order.  Each thread then pairs
+// its row-r columns with their partners read from LDS, writes row r's
+// results to the buffer and row N2 - r's to LDS in place (every LDS word is
+// read and written by one thread only); then the inverse transforms of row
+// N2 - r (from LDS) and of row r (from its own writes).  Rows are left
+// unscaled, as the separate row passes leave them.
+template <class TP, int SRC>
+__global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
+  static_assert(SRC == 0 || SRC == 1, "whiten or fused");
+  constexpr int NT = kN1 / 16, LS = LdsSize<kN1>::value;
+  __shared__ float lds[2 * LS];
+  __shared__ uint32_t sflag;
+  float* sre = lds;
+  float* sim = lds + LS;
+  const int t = threadIdx.x;
+  const DevCfg& cf = a.w.cf;
+  const int NC = a.NC, N2 = a.N2;
+  const int npair = N2 / 2 + 1;
+  const int64_t bd = blockIdx.x / npair;
+  const int rA = int(blockIdx.x - bd * npair);
+  const int rB = rA == 0 ? 0 : N2 - rA;
+  const int64_t b = bd / cf.n_det;
+  const int d = int(bd - b * cf.n_det);
+  float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
+  float2* rowA = buf + int64_t(rA) * kN1;
+  float2* rowB = buf + int64_t(rB) * kN1;
+  const float* psd = a.w.psd + bd * cf.Fw;
+  const cpx<float>* tw1 = reinterpret_cast<const cpx<float>*>(a.tw1);
+  // a fresh table pointer per transform (see opaque)
+  auto tw = [&]() { return PowTwiddle<float, kN1, 0>{opaque(tw1)}; };
+  if (t == 0) sflag = 0u;
+  float cpl = 0.f, cxx = 0.f;
+  double tauT = 0.0;
+  WfScalars wsh;
+  if constexpr (SRC == 1) {
+    wsh = load_const(a.w.wf + b);
+    const DetScalars dsh = load_const(a.w.dsc + (b * cf.n_det + d));
+    cpl = float(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
+    cxx = float(dsh.fx * wsh.cosi);
+    tauT = dsh.tau * cf.invT;
+  }
+  uint32_t flag = 0;
+  cpx<float> v[16];
+  // Each phase below takes its own copy of the lane index and row pointers
+  // (fresh_lane, fresh): without them the compiler shares the index and
+  // address arithmetic of the five transforms and keeps it live throughout,
+  // beyond the 128 registers a 1024-thread workgroup allows.
+  auto load_row = [&](float2* row) {
+    const int tl = fresh_lane(t);
+    float2* r = fresh(row);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float2 q = r[tl + NT * j];
+      v[fft_in_slot<kN1, 0>(j)] = {q.x, q.y};
+    }
+  };
+  auto store_row = [&](float2* row) {
+    const int tl = fresh_lane(t);
+    float2* r = fresh(row);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) r[fft_out_index<kN1, 0>(tl, e)] = {v[e].x, v[e].y};
+  };
+  auto store_lds = [&]() {
+    const int tl = fresh_lane(t);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = lpad<float>(fft_out_index<kN1, 0>(tl, e));
+      sre[i] = v[e].x;
+      sim[i] = v[e].y;
+    }
+  };
+  // forward transform of row rA
+  load_row(rowA);
+  block_fft<float, kN1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+  if (rA == rB) {
+    // self-paired row (uniform over the workgroup): spectrum to LDS, pairs
+    // in LDS, inverse transform from LDS
+    lds_barrier();
+    store_lds();
+    lds_barrier();
+    const int tl = fresh_lane(t);
+#pragma unroll 1
+    for (int j = 0; j < 16; ++j) {
+      const int c = tl + NT * j;
+      const int k = rA + N2 * c, km = NC - k;
+      if (k > km) continue;  // the partner's thread handles the pair
+      const int cm = rA == 0 ? ((kN1 - c) & (kN1 - 1)) : (kN1 - 1 - c);
+      const int ic = lpad<float>(c), im = lpad<float>(cm);
+      cpx<float> A = {sre[ic], sim[ic]}, Bm = {sre[im], sim[im]};
+      long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm, A, Bm, flag);
+      sre[ic] = A.x;
+      sim[ic] = A.y;
+      if (k != 0 && km != k) {
+        sre[im] = Bm.x;
+        sim[im] = Bm.y;
+      }
+    }
+    lds_barrier();
+    block_fft<float, kN1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
+    store_row(rowA);
+  } else {
+    // row rA's spectrum back to its row (columns t + NT j of this thread);
+    // row rB transformed and stored to LDS
+    store_row(rowA);
+    load_row(rowB);
+    lds_barrier();
+    block_fft<float, kN1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+    lds_barrier();
+    store_lds();
+    lds_barrier();
+    {
+      const int tl = fresh_lane(t);
+      float2* ra = fresh(rowA);
+#pragma unroll 1
+      for (int j = 0; j < 16; ++j) {
+        const int c = tl + NT * j;
+        const int cm = kN1 - 1 - c;
+        const int k = rA + N2 * c, km = NC - k;
+        const int im = lpad<float>(cm);
+        const float2 q = ra[c];  // this thread's own write above
+        cpx<float> P = {q.x, q.y}, Q = {sre[im], sim[im]};
+        const int64_t pa = int64_t(rA) * kN1 + c, pb = int64_t(rB) * kN1 + cm;
+        if (k < km) long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, k, pa, pb, P, Q, flag);
+        else long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, km, pb, pa, Q, P, flag);
+        ra[c] = {P.x, P.y};
+        sre[im] = Q.x;
+        sim[im] = Q.y;
+      }
+    }
+    lds_barrier();
+    block_fft<float, kN1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
+    store_row(rowB);
+    // row rA: its bins as this thread wrote them, in the transform's input layout
+    load_row(rowA);
+    lds_barrier();
+    block_fft<float, kN1, +1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+    store_row(rowA);
+  }
+  if (flag) atomicOr(&sflag, flag);
+  __syncthreads();
+  if (t == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
+}
+
 template <int SRC>
 void launch_cols_fwd(const LongArgs& a, int64_t items, hipStream_t st) {
   const dim3 grid(unsigned(kN1 / 256), unsigned(items));
@@ -340,6 +546,15 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   }
   if (src == 0) launch_cols_fwd<0>(a, items, st);
   else launch_cols_fwd<1>(a, items, st);
+  if (d.ord_win) {
+    // rows, bins and inverse rows fused per row pair
+    const dim3 pair_grid(unsigned(items * (a.N2 / 2 + 1)));
+    if (src == 0) hipLaunchKernelGGL((k_long_rowpair<double, 0>), pair_grid, dim3(kN1 / 16), 0, st, a);
+    else if (d.precision == 0) hipLaunchKernelGGL((k_long_rowpair<float, 1>), pair_grid, dim3(kN1 / 16), 0, st, a);
+    else hipLaunchKernelGGL((k_long_rowpair<double, 1>), pair_grid, dim3(kN1 / 16), 0, st, a);
+    launch_cols_inv<0>(a, items, st);
+    return ctx_check_launch(c, "long window");
+  }
   hipLaunchKernelGGL((k_long_rows<-1>), rows_grid, dim3(kN1 / 16), 0, st, a);
   if (src == 0) {
     hipLaunchKernelGGL((k_long_bins<double, 0>), bins_grid, dim3(256), 0, st, a);

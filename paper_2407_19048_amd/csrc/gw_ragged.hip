@@ -72,20 +72,6 @@ struct gw_ragged {
 namespace {
 
 // ------------------------------------------------------------ device side
-// Returns p unchanged, but the compiler can no longer prove it loop
-// invariant: loads through it stay inside the persistent loop instead of
-// being hoisted (with every pass's twiddles then live at once).  p points to
-// global memory and is laundered as a global pointer, so that loads through
-// it remain global loads: through a generic pointer they would become flat
-// loads, which also count against the LDS wait counter and make every LDS
-// barrier wait for them.
-template <class T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  typedef const __attribute__((address_space(1))) T* gptr;
-  gptr g = (gptr)p;
-  asm volatile("" : "+s"(g));
-  return (const T*)g;
-}
 
 struct RSampleArgs {
   const DevCfg* cfgs;

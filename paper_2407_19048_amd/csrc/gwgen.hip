@@ -579,7 +579,8 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   // paper-scale shape (binary32 transforms of L = 4096 fit 3 waves per SIMD
   // without spills; the 8192-point window prefers its radix-2 pass first)
   c.occ_welch = (c.L == 4096 && c.precision != 2) ? 3 : 2;
-  c.ord_win = (c.N == 16384 && c.precision != 2) ? 1 : 0;
+  // windows longer than 32768 samples: 1 selects the fused row-pair pass
+  c.ord_win = ((c.N == 16384 || c.N > 32768) && c.precision != 2) ? 1 : 0;
   for (int d = 0; d < g->n_det; ++d) c.det[d] = make_detector(g->det_id[d]);
   *dc = c;
   return GW_OK;

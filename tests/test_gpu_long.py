@@ -192,3 +192,32 @@ def test_long_windows_reject_unsupported_paths():
     with pytest.raises(gwgen.GWError):
         gen.whiten_filter(torch.ones((3, gen.sizes["Fw"]), dtype=torch.float32, device=DEV), 64,
                           torch.empty((3, gen.sizes["F"]), dtype=torch.float32, device=DEV))
+
+
+@pytest.mark.parametrize("structure", [0, 1])
+def test_long_window_structures_match_oracle(structure):
+    """Both structures of the four-step window stage (0: row transforms, bins
+    and inverse rows as three passes; 1: fused per row pair) against the
+    oracle, at N2 = 8 (rows 0 and 4 self-paired, rows 1-3 paired with 7-5)."""
+    cfg = inputs.config("bns_long", t_window=128.0)
+    N = int(cfg["t_window"] * cfg["fs"])
+    bg_np = bg_for(2048.0, 22)
+    gen = gwgen.Generator(cfg)
+    gen.set_tuning(gwgen.TUNE_ORD_WINDOW, structure)
+    B = 2
+    out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
+    ws = gen.alloc_workspace(B)
+    _say("long structure %d N=%d" % (structure, N))
+    gen.generate_batch(6, 2, B, torch.from_numpy(bg_np).to(DEV), out, ws)
+    torch.cuda.synchronize()
+    params, offs = gen.workspace_views(ws, B)
+    P, O = checked_draws(cfg, 6, 2 * B, params.cpu().numpy(), offs.cpu().numpy(), bg_np.shape[1])
+    G = out.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        ref = pipeline.generate_sample(cfg, bg_np, P[:, i], int(O[i]))
+        for d in range(3):
+            e = rel_l2(G[i, d], ref[d])
+            worst = max(worst, e)
+            assert e <= 1e-5, (structure, i, d, e)
+    _say("long structure %d worst rel L2 %.3e" % (structure, worst))
