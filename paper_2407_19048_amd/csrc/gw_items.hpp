@@ -269,11 +269,15 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       __builtin_memcpy(&q, x + 2 * (t + NT * j), sizeof(q));
       v[fft_in_slot<NC, ORD>(j)] = {T(q.x), T(q.y)};
     }
-    block_fft<T, NC, -1, false, ORD>(v, sre, sim, t, tw);
+    // fresh lane indices and a fresh table pointer per transform: otherwise
+    // the compiler shares the forward and inverse transforms' index
+    // arithmetic and twiddle loads and keeps them live in between
+    block_fft<T, NC, -1, false, ORD>(v, sre, sim, fresh_lane(t), tw);
     lds_barrier();
+    const int tn = fresh_lane(t);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int i = lpad<T>(fft_out_index<NC, ORD>(t, e));
+      const int i = lpad<T>(fft_out_index<NC, ORD>(tn, e));
       sre[i] = v[e].x;
       sim[i] = v[e].y;
     }
@@ -394,7 +398,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     }
   }
   lds_barrier();
-  block_fft<T, NC, +1, true, ORD>(v, sre, sim, t, tw);
+  block_fft<T, NC, +1, true, ORD>(v, sre, sim, fresh_lane(t), PowTwiddle<T, NC, ORD>{opaque(twtab)});
   const T sc = T(1) / T(NC);
   if (active) {
 #pragma unroll

@@ -307,31 +307,6 @@ __device__ __forceinline__ void long_pair(const LongArgs& a, const WfScalars& ws
   Bm = {p.x + q.y, -p.y + q.x};
 }
 
-// p (uniform over the workgroup) unchanged, but addresses derived from it are
-// not shared with (and kept live across) other phases of the kernel that use
-// the same pointer.
-template <class T>
-__device__ __forceinline__ T* fresh(T* p) {
-  typedef __attribute__((address_space(1))) T* gptr;
-  const uint64_t u = reinterpret_cast<uint64_t>(p);
-  // readfirstlane works on (signed) int: widen its result as unsigned, or a
-  // low word with the top bit set would sign-extend into the high word
-  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u))));
-  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u >> 32))));
-  const uint64_t s = uint64_t(lo) | (uint64_t(hi) << 32);
-  gptr g = (gptr)reinterpret_cast<T*>(s);
-  asm volatile("" : "+s"(g));
-  return (T*)g;
-}
-
-// The lane index t, unchanged, as a value the compiler cannot prove equal to
-// t elsewhere: index and LDS-address arithmetic of one phase is then not
-// shared with (and kept live across) the other phases.
-__device__ __forceinline__ int fresh_lane(int t) {
-  asm volatile("" : "+v"(t));
-  return t;
-}
-
 // Rows, bins and inverse rows of one row pair in one workgroup (replacing
 // three passes through HBM).  Bin k = r + N2 c sits at row r, column c of the
 // transposed spectrum, and its partner NC - k at row N2 - r, column N1 - 1 - c
