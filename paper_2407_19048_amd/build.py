@@ -54,5 +54,34 @@ def build(verbose=True):
     return OUT
 
 
+def build_host_sanitized(out, verbose=False):
+    """The library with its host side built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code unsanitized, at -O1), for
+    checking the host-side argument validation and bookkeeping on a machine
+    without a GPU.  Loaded with the sanitizer runtime preloaded."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    flags = ["--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC", "-Xarch_host", "-g"] + san
+    objs, procs = [], []
+    for src in SRCS:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(src))[0] + ".asan.o")
+        cmd = [hipcc] + flags + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+        objs.append(obj)
+    for src, p in zip(SRCS, procs):
+        text, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("hipcc failed on %s:\n%s" % (os.path.basename(src), text))
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + san + ["-o", out] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
+    return out
+
+
 if __name__ == "__main__":
     build()

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgwgen.so")
+# the in-tree library; GWGEN_LIB names another build of it (the host-only
+# sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("GWGEN_LIB") or os.path.join(_HERE, "libgwgen.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EHIP, GW_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS_NONFINITE_PSD = 1
