@@ -278,28 +278,56 @@ __global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
   if (threadIdx.x == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
 }
 
-// One pair of packed-spectrum bins (k, km = NC - k), k <= NC/2: A = Z[k] and
-// Bm = Z[km] in; out, the packed spectrum of the whitened window (SRC 1 with
-// the in-register signal added) at the same two bins.  pk, pm: positions of k
+// Global inputs of one pair of packed-spectrum bins (k, km = NC - k),
+// k <= NC/2: the real-FFT twiddle exp(-2 pi i k / N), the bin tables of both
+// bins (SRC 1) and the PSD values around both bins.  pk, pm: positions of k
 // and km in the transposed bin tables.
-template <class TP, int SRC>
-__device__ __forceinline__ void long_pair(const LongArgs& a, const WfScalars& wsh, float cpl, float cxx, double tauT,
-                                          const float* psd, int k, int64_t pk, int64_t pm, cpx<float>& A,
-                                          cpx<float>& Bm, uint32_t& flag) {
+struct LongPairIn {
+  cpx<float> W;
+  double kc[2], lk[2];
+  float g[4];
+};
+
+template <int SRC>
+__device__ __forceinline__ LongPairIn long_pair_fetch(const LongArgs& a, const float* psd, int k, int64_t pk,
+                                                      int64_t pm) {
   const DevCfg& cf = a.w.cf;
   const int NC = a.NC, km = NC - k;
-  const cpx<float> W = a.twr_t[pk];  // exp(-2 pi i k / N)
+  LongPairIn in;
+  in.W = a.twr_t[pk];
+  if constexpr (SRC == 1) {
+    in.kc[0] = a.kc_t[pk];
+    in.lk[0] = a.lk_t[pk];
+    in.kc[1] = a.kc_t[pm];
+    in.lk[1] = a.lk_t[pm];
+  }
+  const int ia = psd_index(cf, k, NC), ib = psd_index(cf, km, NC);
+  in.g[0] = psd[ia];
+  in.g[1] = psd[ia + 1];
+  in.g[2] = psd[ib];
+  in.g[3] = psd[ib + 1];
+  return in;
+}
+
+// One pair of packed-spectrum bins (k, km = NC - k), k <= NC/2: A = Z[k] and
+// Bm = Z[km] in; out, the packed spectrum of the whitened window (SRC 1 with
+// the in-register signal added) at the same two bins.
+template <class TP, int SRC>
+__device__ __forceinline__ void long_pair(const LongArgs& a, const WfScalars& wsh, float cpl, float cxx, double tauT,
+                                          const LongPairIn& in, int k, cpx<float>& A, cpx<float>& Bm, uint32_t& flag) {
+  const DevCfg& cf = a.w.cf;
+  const int NC = a.NC, km = NC - k;
+  const cpx<float> W = in.W;  // exp(-2 pi i k / N)
   const cpx<float> s = cadd(A, cconj(Bm));
   const cpx<float> u = cmul(W, csub(A, cconj(Bm)));
   cpx<float> Xk = {0.5f * (s.x + u.y), 0.5f * (s.y - u.x)};
   cpx<float> Xm = {0.5f * (s.x - u.y), 0.5f * (-s.y - u.x)};
   if constexpr (SRC == 1) {
-    Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, k, a.kc_t[pk], a.lk_t[pk]));
-    if (km != k) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, a.kc_t[pm], a.lk_t[pm]));
+    Xk = cadd(Xk, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, k, in.kc[0], in.lk[0]));
+    if (km != k) Xm = cadd(Xm, signal_bin_at<float, TP, false>(cf, wsh, cpl, cxx, tauT, km, in.kc[1], in.lk[1]));
   }
-  const int ia = psd_index(cf, k, NC), ib = psd_index(cf, km, NC);
-  const cpx<float> Yk = cscale(Xk, whiten_gain_at<float>(cf, psd[ia], psd[ia + 1], k, NC, flag));
-  cpx<float> Ym = cscale(Xm, whiten_gain_at<float>(cf, psd[ib], psd[ib + 1], km, NC, flag));
+  const cpx<float> Yk = cscale(Xk, whiten_gain_at<float>(cf, in.g[0], in.g[1], k, NC, flag));
+  cpx<float> Ym = cscale(Xm, whiten_gain_at<float>(cf, in.g[2], in.g[3], km, NC, flag));
   if (km == k) Ym = Yk;
   const cpx<float> p = cscale(cadd(Yk, cconj(Ym)), 0.5f);
   const cpx<float> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), 0.5f), W);
@@ -397,18 +425,40 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
     store_lds();
     lds_barrier();
     const int tl = fresh_lane(t);
+    // column of iteration j and its mirror; the pair's global inputs are
+    // fetched one iteration ahead (clamped to the lower bin, so that every
+    // iteration loads a valid pair) to overlap their latency
+    auto cols = [&](int j, int& c, int& cm, int& k) {
+      c = tl + NT * j;
+      cm = rA == 0 ? ((kN1 - c) & (kN1 - 1)) : (kN1 - 1 - c);
+      k = rA + N2 * c;
+      if (k > NC - k) {  // the partner's thread handles the pair; fetch it anyway
+        const int x = c;
+        c = cm;
+        cm = x;
+        k = NC - k;
+      }
+    };
+    int c, cm, k;
+    cols(0, c, cm, k);
+    LongPairIn nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm);
 #pragma unroll 1
     for (int j = 0; j < 16; ++j) {
-      const int c = tl + NT * j;
-      const int k = rA + N2 * c, km = NC - k;
-      if (k > km) continue;  // the partner's thread handles the pair
-      const int cm = rA == 0 ? ((kN1 - c) & (kN1 - 1)) : (kN1 - 1 - c);
-      const int ic = lpad<float>(c), im = lpad<float>(cm);
+      const LongPairIn cur = nxt;
+      const int cj = c, cmj = cm, kj = k;
+      const bool mine = rA + N2 * (tl + NT * j) <= NC - (rA + N2 * (tl + NT * j));
+      if (j + 1 < 16) {
+        cols(j + 1, c, cm, k);
+        nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm);
+      }
+      if (!mine) continue;  // the partner's thread handles the pair
+      const int km = NC - kj;
+      const int ic = lpad<float>(cj), im = lpad<float>(cmj);
       cpx<float> A = {sre[ic], sim[ic]}, Bm = {sre[im], sim[im]};
-      long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm, A, Bm, flag);
+      long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, cur, kj, A, Bm, flag);
       sre[ic] = A.x;
       sim[ic] = A.y;
-      if (k != 0 && km != k) {
+      if (kj != 0 && km != kj) {
         sre[im] = Bm.x;
         sim[im] = Bm.y;
       }
@@ -429,17 +479,34 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
     {
       const int tl = fresh_lane(t);
       float2* ra = fresh(rowA);
+      // the pair's global inputs (own row-r bin, tables, PSD values) are
+      // fetched one iteration ahead to overlap their latency
+      struct Ahead {
+        float2 q;
+        LongPairIn in;
+      };
+      auto fetch = [&](int j) {
+        const int c = tl + NT * j;
+        const int cm = kN1 - 1 - c;
+        const int k = rA + N2 * c, km = NC - k;
+        const int64_t pa = int64_t(rA) * kN1 + c, pb = int64_t(rB) * kN1 + cm;
+        Ahead h;
+        h.q = ra[c];  // this thread's own write above
+        h.in = k < km ? long_pair_fetch<SRC>(a, psd, k, pa, pb) : long_pair_fetch<SRC>(a, psd, km, pb, pa);
+        return h;
+      };
+      Ahead nxt = fetch(0);
 #pragma unroll 1
       for (int j = 0; j < 16; ++j) {
+        const Ahead cur = nxt;
+        if (j + 1 < 16) nxt = fetch(j + 1);
         const int c = tl + NT * j;
         const int cm = kN1 - 1 - c;
         const int k = rA + N2 * c, km = NC - k;
         const int im = lpad<float>(cm);
-        const float2 q = ra[c];  // this thread's own write above
-        cpx<float> P = {q.x, q.y}, Q = {sre[im], sim[im]};
-        const int64_t pa = int64_t(rA) * kN1 + c, pb = int64_t(rB) * kN1 + cm;
-        if (k < km) long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, k, pa, pb, P, Q, flag);
-        else long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, psd, km, pb, pa, Q, P, flag);
+        cpx<float> P = {cur.q.x, cur.q.y}, Q = {sre[im], sim[im]};
+        if (k < km) long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, cur.in, k, P, Q, flag);
+        else long_pair<TP, SRC>(a, wsh, cpl, cxx, tauT, cur.in, km, Q, P, flag);
         ra[c] = {P.x, P.y};
         sre[im] = Q.x;
         sim[im] = Q.y;
