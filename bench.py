@@ -471,6 +471,7 @@ def main():
             % (cpu["value"], cpu["cores"], cpu["one_core"], cpu["cpu_model"], cpu["host_cores_usable"],
                cpu["host_cores_reported"]))
 
+    import numpy as np
     import torch
     from paper_2407_19048_amd import gwgen
     gwgen.lib()
@@ -504,6 +505,17 @@ def main():
     ms_step = 1e3 * elapsed / K
     if not bool(torch.isfinite(out).all()):
         raise RuntimeError("non-finite output")
+    # per-replay times with events around each graph launch (outside the
+    # timed region): median and spread of single batches
+    pairs_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for e0, e1 in pairs_ev:
+        e0.record()
+        graph.launch()
+        e1.record()
+    torch.cuda.synchronize()
+    per_ms = np.array([e0.elapsed_time(e1) for e0, e1 in pairs_ev])
+    log("graph replay events: median %.4f ms, p10 %.4f, p90 %.4f over %d replays"
+        % (np.median(per_ms), np.percentile(per_ms, 10), np.percentile(per_ms, 90), K))
     # the same batches issued eagerly (three launches per step), for comparison
     Ke = min(K, 20)
     torch.cuda.synchronize()
@@ -607,6 +619,9 @@ def main():
             "path": "plain",
             "issue": "hip graph replay",
             "eager_ms_per_step": round(eager_ms, 4),
+            "replay_event_ms": {"median": round(float(np.median(per_ms)), 4),
+                                "p10": round(float(np.percentile(per_ms, 10)), 4),
+                                "p90": round(float(np.percentile(per_ms, 90)), 4), "n": int(K)},
             "autotune_ms": {k: round(v, 4) for k, v in tune.items()},
             "tuned": tuned,
             "step_hbm_frac_algorithmic": round(step_gbs / HBM_PEAK_GBS, 4),

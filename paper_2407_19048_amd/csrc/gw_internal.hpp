@@ -17,7 +17,7 @@ struct gw_ctx {
   void* tw_win = nullptr;     // cpx<T>[N/2]
   void* twr_win = nullptr;    // cpx<T>[N/4 + 1]
   void* tw_welch = nullptr;   // cpx<T>[L]
-  void* tw_long = nullptr;    // cpx<float>[N2][16384]: W_NC^(m1 k2), windows longer than 32768 samples
+  void* tw_long = nullptr;    // cpx<float>[N2][N1]: W_NC^(m1 k2), windows longer than 32768 samples
   // windows longer than 32768 samples: k^(1/3), ln(k)/3 (double[N/2] each) and
   // exp(-2 pi i k / N) (cpx<float>[N/2]) for k < N/2, stored at the position
   // (k mod N2) N1 + k / N2 of bin k in the transposed four-step spectrum
@@ -44,6 +44,8 @@ gw_status ctx_fail(gw_ctx* c, gw_status s, const std::string& msg);
 // in the output buffer): src 0 whiten, 1 fused batch, 2 inject.
 gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, const float* hdet, int64_t items,
                       hipStream_t st);
+// Row length N1 of the four-step split NC = N1 x N2 of those windows.
+int long_row_length(int NC);
 gw_status ctx_check_launch(gw_ctx* c, const char* what);
 // Host validation of a configuration into device constants (nothing launched).
 gw_status validate_config(const gw_config* g, DevCfg* dc, std::string* why);

@@ -1,8 +1,10 @@
 // Long windows (N > 32768 samples, e.g. long-duration binary-neutron-star
 // signals): the half-length complex transform of NC = N/2 points no longer
 // fits in one workgroup's LDS and runs as a four-step FFT through HBM, with
-// NC = N1 x N2, N1 = 16384 (one workgroup transform in LDS) and N2 = NC/N1
-// in {2, 4, 8, 16, 32} (in registers).  With c[m] = y[2m] + i y[2m+1]:
+// NC = N1 x N2, N1 the row length (one workgroup transform in LDS) and
+// N2 = NC/N1 in {4, 8, 16, 32} (in registers).  N1 = 8192 up to N = 2^19
+// (two workgroups of 512 threads share a CU), 16384 for N = 2^20 (N2 = 32).
+// With c[m] = y[2m] + i y[2m+1]:
 //
 //   forward  columns  w[k2][m1] = W_NC^(m1 k2) sum_m2 c[m1 + N1 m2] W_N2^(m2 k2)
 //            rows     X[k2 + N2 k1] = sum_m1 w[k2][m1] W_N1^(m1 k1)   (in place)
@@ -30,7 +32,9 @@ using namespace gw;
 
 namespace {
 
-constexpr int kN1 = 16384;
+// Waves per SIMD the row kernels are compiled for: two 512-thread workgroups
+// (N1 = 8192) or one 1024-thread workgroup (N1 = 16384) per CU, 128 VGPRs.
+constexpr int kRowWaves = 4;
 
 // In-register DFT of length R (natural order in and out), DIR = -1 forward.
 template <int R, int DIR, class T>
@@ -85,7 +89,7 @@ __device__ __forceinline__ const float* long_input(const LongArgs& a, int64_t bd
 }
 
 // Forward columns: one thread per column m1, grid (N1/256, B*D).
-template <int N2, int SRC>
+template <int N1, int N2, int SRC>
 __global__ __launch_bounds__(256) void k_long_cols_fwd(LongArgs a) {
   const int m1 = blockIdx.x * 256 + threadIdx.x;
   const int64_t bd = blockIdx.y;
@@ -96,20 +100,20 @@ __global__ __launch_bounds__(256) void k_long_cols_fwd(LongArgs a) {
 #pragma unroll
   for (int m2 = 0; m2 < N2; ++m2) {
     float2 q;
-    __builtin_memcpy(&q, x + 2 * (int64_t(m1) + int64_t(kN1) * m2), sizeof(q));
+    __builtin_memcpy(&q, x + 2 * (int64_t(m1) + int64_t(N1) * m2), sizeof(q));
     v[m2] = {q.x, q.y};
   }
   dft_small<N2, -1>(v);
 #pragma unroll
   for (int k2 = 0; k2 < N2; ++k2) {
-    const cpx<float> w = k2 ? cmul(v[k2], twc[k2 * kN1 + m1]) : v[k2];
-    buf[int64_t(k2) * kN1 + m1] = {w.x, w.y};
+    const cpx<float> w = k2 ? cmul(v[k2], twc[k2 * N1 + m1]) : v[k2];
+    buf[int64_t(k2) * N1 + m1] = {w.x, w.y};
   }
 }
 
 // Inverse columns: twiddle, inverse DFT over k2, scale 1/NC, store real
 // samples in place; SRC 2 adds the noise window.
-template <int N2, int SRC>
+template <int N1, int N2, int SRC>
 __global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
   const int m1 = blockIdx.x * 256 + threadIdx.x;
   const int64_t bd = blockIdx.y;
@@ -118,9 +122,9 @@ __global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
   cpx<float> v[N2];
 #pragma unroll
   for (int k2 = 0; k2 < N2; ++k2) {
-    const float2 q = buf[int64_t(k2) * kN1 + m1];
+    const float2 q = buf[int64_t(k2) * N1 + m1];
     const cpx<float> u = {q.x, q.y};
-    v[k2] = k2 ? twmul<+1>(u, twc[k2 * kN1 + m1]) : u;
+    v[k2] = k2 ? twmul<+1>(u, twc[k2 * N1 + m1]) : u;
   }
   dft_small<N2, +1>(v);
   const float sc = 1.f / float(a.NC);
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
   if constexpr (SRC == 2) nz = long_input<2>(a, bd);
 #pragma unroll
   for (int m2 = 0; m2 < N2; ++m2) {
-    const int64_t m = int64_t(m1) + int64_t(kN1) * m2;
+    const int64_t m = int64_t(m1) + int64_t(N1) * m2;
     float2 y = {v[m2].x * sc, v[m2].y * sc};
     if constexpr (SRC == 2) {
       y.x += nz[2 * m];
@@ -139,28 +143,29 @@ __global__ __launch_bounds__(256) void k_long_cols_inv(LongArgs a) {
 }
 
 // Row transforms of length N1 in place: grid B*D*N2 workgroups of N1/16.
-template <int DIR>
-__global__ __launch_bounds__(kN1 / 16) void k_long_rows(LongArgs a) {
-  constexpr int NT = kN1 / 16, LS = LdsSize<kN1>::value;
+template <int N1, int DIR>
+__global__ __launch_bounds__(N1 / 16, kRowWaves) void k_long_rows(LongArgs a) {
+  constexpr int NT = N1 / 16, LS = LdsSize<N1>::value;
   __shared__ float lds[2 * LS];
   const int t = threadIdx.x;
-  float2* row = reinterpret_cast<float2*>(a.w.out) + int64_t(blockIdx.x) * kN1;
-  PowTwiddle<float, kN1, 0> tw{reinterpret_cast<const cpx<float>*>(a.tw1)};
+  float2* row = reinterpret_cast<float2*>(a.w.out) + int64_t(blockIdx.x) * N1;
+  PowTwiddle<float, N1, 0> tw{reinterpret_cast<const cpx<float>*>(a.tw1)};
   cpx<float> v[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const float2 q = row[t + NT * j];
-    v[fft_in_slot<kN1, 0>(j)] = {q.x, q.y};
+    v[fft_in_slot<N1, 0>(j)] = {q.x, q.y};
   }
-  block_fft<float, kN1, DIR, false, 0>(v, lds, lds + LS, t, tw);
+  block_fft<float, N1, DIR, false, 0>(v, lds, lds + LS, t, tw);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) row[fft_out_index<kN1, 0>(t, e)] = {v[e].x, v[e].y};
+  for (int e = 0; e < 16; ++e) row[fft_out_index<N1, 0>(t, e)] = {v[e].x, v[e].y};
 }
 
 // Inject: pack the given projected spectrum for the inverse transform, one
 // thread per pair (k, NC - k), k in [0, NC/2], reading hdet by k:
 // grid (ceil((NC/2 + 1)/256), B*D).  The packed pair lands at its place in
 // the transposed layout X'[k2][k1] = X[k2 + N2 k1] of the inverse rows.
+template <int N1>
 __global__ __launch_bounds__(256) void k_long_inject(LongArgs a, const float* hdet) {
   const int64_t bd = blockIdx.y;
   const int NC = a.NC, N2 = a.N2;
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(256) void k_long_inject(LongArgs a, const float* hd
   if (k > NC / 2) return;
   float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
   const int km = NC - k;
-  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
+  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * N1 + (kk >> a.l2n2); };
   const cpx<float> W = reinterpret_cast<const cpx<float>*>(a.twr)[k];  // exp(-2 pi i k / N)
   const float2* h = reinterpret_cast<const float2*>(hdet) + bd * (NC + 1);
   const float2 h0 = h[k], h1 = h[km];
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(256) void k_long_inject(LongArgs a, const float* hd
 // inputs are loaded before either is computed, so the second pair's loads
 // overlap the first pair's arithmetic.  Idle lanes load a real pair too (k is
 // clamped into range) and only skip their stores.
-template <class TP, int SRC>
+template <int N1, class TP, int SRC>
 __global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
   static_assert(SRC == 0 || SRC == 1, "whiten or fused");
   constexpr int J = 2;
@@ -205,7 +210,7 @@ __global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
   const int d = int(bd - b * cf.n_det);
   float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
   const float* psd = a.w.psd + bd * cf.Fw;
-  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * kN1 + (kk >> a.l2n2); };
+  auto pos = [&](int kk) { kk &= NC - 1; return int64_t(kk & (N2 - 1)) * N1 + (kk >> a.l2n2); };
   __shared__ uint32_t sflag;
   if (threadIdx.x == 0) sflag = 0u;
   __syncthreads();
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(256) void k_long_bins(LongArgs a) {
   for (int j = 0; j < J; ++j) {
     const int k1 = blockIdx.x * (256 * J) + 256 * j + threadIdx.x;  // < N1
     const int kr = r + N2 * k1;
-    ok[j] = (r == 0) ? (k1 <= kN1 / 2) : (2 * r == N2) ? (k1 < kN1 / 2) : true;
+    ok[j] = (r == 0) ? (k1 <= N1 / 2) : (2 * r == N2) ? (k1 < N1 / 2) : true;
     k[j] = min(kr, NC - kr);
     const int km = NC - k[j];
     const int64_t pk = pos(k[j]), pm = pos(km);
@@ -350,10 +355,10 @@ __device__ __forceinline__ void long_pair(const LongArgs& a, const WfScalars& ws
 // read and written by one thread only); then the inverse transforms of row
 // N2 - r (from LDS) and of row r (from its own writes).  Rows are left
 // unscaled, as the separate row passes leave them.
-template <class TP, int SRC>
-__global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
+template <int N1, class TP, int SRC>
+__global__ __launch_bounds__(N1 / 16, kRowWaves) void k_long_rowpair(LongArgs a) {
   static_assert(SRC == 0 || SRC == 1, "whiten or fused");
-  constexpr int NT = kN1 / 16, LS = LdsSize<kN1>::value;
+  constexpr int NT = N1 / 16, LS = LdsSize<N1>::value;
   __shared__ float lds[2 * LS];
   __shared__ uint32_t sflag;
   float* sre = lds;
@@ -368,12 +373,12 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
   const int64_t b = bd / cf.n_det;
   const int d = int(bd - b * cf.n_det);
   float2* buf = reinterpret_cast<float2*>(a.w.out) + bd * NC;
-  float2* rowA = buf + int64_t(rA) * kN1;
-  float2* rowB = buf + int64_t(rB) * kN1;
+  float2* rowA = buf + int64_t(rA) * N1;
+  float2* rowB = buf + int64_t(rB) * N1;
   const float* psd = a.w.psd + bd * cf.Fw;
   const cpx<float>* tw1 = reinterpret_cast<const cpx<float>*>(a.tw1);
   // a fresh table pointer per transform (see opaque)
-  auto tw = [&]() { return PowTwiddle<float, kN1, 0>{opaque(tw1)}; };
+  auto tw = [&]() { return PowTwiddle<float, N1, 0>{opaque(tw1)}; };
   if (t == 0) sflag = 0u;
   float cpl = 0.f, cxx = 0.f;
   double tauT = 0.0;
@@ -397,27 +402,27 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const float2 q = r[tl + NT * j];
-      v[fft_in_slot<kN1, 0>(j)] = {q.x, q.y};
+      v[fft_in_slot<N1, 0>(j)] = {q.x, q.y};
     }
   };
   auto store_row = [&](float2* row) {
     const int tl = fresh_lane(t);
     float2* r = fresh(row);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) r[fft_out_index<kN1, 0>(tl, e)] = {v[e].x, v[e].y};
+    for (int e = 0; e < 16; ++e) r[fft_out_index<N1, 0>(tl, e)] = {v[e].x, v[e].y};
   };
   auto store_lds = [&]() {
     const int tl = fresh_lane(t);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const int i = lpad<float>(fft_out_index<kN1, 0>(tl, e));
+      const int i = lpad<float>(fft_out_index<N1, 0>(tl, e));
       sre[i] = v[e].x;
       sim[i] = v[e].y;
     }
   };
   // forward transform of row rA
   load_row(rowA);
-  block_fft<float, kN1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+  block_fft<float, N1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
   if (rA == rB) {
     // self-paired row (uniform over the workgroup): spectrum to LDS, pairs
     // in LDS, inverse transform from LDS
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
     // iteration loads a valid pair) to overlap their latency
     auto cols = [&](int j, int& c, int& cm, int& k) {
       c = tl + NT * j;
-      cm = rA == 0 ? ((kN1 - c) & (kN1 - 1)) : (kN1 - 1 - c);
+      cm = rA == 0 ? ((N1 - c) & (N1 - 1)) : (N1 - 1 - c);
       k = rA + N2 * c;
       if (k > NC - k) {  // the partner's thread handles the pair; fetch it anyway
         const int x = c;
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
     };
     int c, cm, k;
     cols(0, c, cm, k);
-    LongPairIn nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm);
+    LongPairIn nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * N1 + c, int64_t(rA) * N1 + cm);
 #pragma unroll 1
     for (int j = 0; j < 16; ++j) {
       const LongPairIn cur = nxt;
@@ -449,7 +454,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
       const bool mine = rA + N2 * (tl + NT * j) <= NC - (rA + N2 * (tl + NT * j));
       if (j + 1 < 16) {
         cols(j + 1, c, cm, k);
-        nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * kN1 + c, int64_t(rA) * kN1 + cm);
+        nxt = long_pair_fetch<SRC>(a, psd, k, int64_t(rA) * N1 + c, int64_t(rA) * N1 + cm);
       }
       if (!mine) continue;  // the partner's thread handles the pair
       const int km = NC - kj;
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
       }
     }
     lds_barrier();
-    block_fft<float, kN1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
+    block_fft<float, N1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
     store_row(rowA);
   } else {
     // row rA's spectrum back to its row (columns t + NT j of this thread);
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
     store_row(rowA);
     load_row(rowB);
     lds_barrier();
-    block_fft<float, kN1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+    block_fft<float, N1, -1, false, 0>(v, sre, sim, fresh_lane(t), tw());
     lds_barrier();
     store_lds();
     lds_barrier();
@@ -487,9 +492,9 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
       };
       auto fetch = [&](int j) {
         const int c = tl + NT * j;
-        const int cm = kN1 - 1 - c;
+        const int cm = N1 - 1 - c;
         const int k = rA + N2 * c, km = NC - k;
-        const int64_t pa = int64_t(rA) * kN1 + c, pb = int64_t(rB) * kN1 + cm;
+        const int64_t pa = int64_t(rA) * N1 + c, pb = int64_t(rB) * N1 + cm;
         Ahead h;
         h.q = ra[c];  // this thread's own write above
         h.in = k < km ? long_pair_fetch<SRC>(a, psd, k, pa, pb) : long_pair_fetch<SRC>(a, psd, km, pb, pa);
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
         const Ahead cur = nxt;
         if (j + 1 < 16) nxt = fetch(j + 1);
         const int c = tl + NT * j;
-        const int cm = kN1 - 1 - c;
+        const int cm = N1 - 1 - c;
         const int k = rA + N2 * c, km = NC - k;
         const int im = lpad<float>(cm);
         cpx<float> P = {cur.q.x, cur.q.y}, Q = {sre[im], sim[im]};
@@ -513,12 +518,12 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
       }
     }
     lds_barrier();
-    block_fft<float, kN1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
+    block_fft<float, N1, +1, true, 0>(v, sre, sim, fresh_lane(t), tw());
     store_row(rowB);
     // row rA: its bins as this thread wrote them, in the transform's input layout
     load_row(rowA);
     lds_barrier();
-    block_fft<float, kN1, +1, false, 0>(v, sre, sim, fresh_lane(t), tw());
+    block_fft<float, N1, +1, false, 0>(v, sre, sim, fresh_lane(t), tw());
     store_row(rowA);
   }
   if (flag) atomicOr(&sflag, flag);
@@ -526,33 +531,76 @@ __global__ __launch_bounds__(kN1 / 16) void k_long_rowpair(LongArgs a) {
   if (t == 0 && sflag && a.w.status) atomicOr(a.w.status + b, sflag);
 }
 
-template <int SRC>
+template <int N1, int SRC>
 void launch_cols_fwd(const LongArgs& a, int64_t items, hipStream_t st) {
-  const dim3 grid(unsigned(kN1 / 256), unsigned(items));
-  switch (a.N2) {
-    case 2: hipLaunchKernelGGL((k_long_cols_fwd<2, SRC>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_long_cols_fwd<4, SRC>), grid, dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_long_cols_fwd<8, SRC>), grid, dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_long_cols_fwd<16, SRC>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_long_cols_fwd<32, SRC>), grid, dim3(256), 0, st, a); break;
+  const dim3 grid(unsigned(N1 / 256), unsigned(items));
+  if constexpr (N1 == 16384) {  // only N = 2^20 uses rows of 16384
+    hipLaunchKernelGGL((k_long_cols_fwd<N1, 32, SRC>), grid, dim3(256), 0, st, a);
+  } else {
+    switch (a.N2) {
+      case 4: hipLaunchKernelGGL((k_long_cols_fwd<N1, 4, SRC>), grid, dim3(256), 0, st, a); break;
+      case 8: hipLaunchKernelGGL((k_long_cols_fwd<N1, 8, SRC>), grid, dim3(256), 0, st, a); break;
+      case 16: hipLaunchKernelGGL((k_long_cols_fwd<N1, 16, SRC>), grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_long_cols_fwd<N1, 32, SRC>), grid, dim3(256), 0, st, a); break;
+    }
   }
 }
 
-template <int SRC>
+template <int N1, int SRC>
 void launch_cols_inv(const LongArgs& a, int64_t items, hipStream_t st) {
-  const dim3 grid(unsigned(kN1 / 256), unsigned(items));
-  switch (a.N2) {
-    case 2: hipLaunchKernelGGL((k_long_cols_inv<2, SRC>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_long_cols_inv<4, SRC>), grid, dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_long_cols_inv<8, SRC>), grid, dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_long_cols_inv<16, SRC>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_long_cols_inv<32, SRC>), grid, dim3(256), 0, st, a); break;
+  const dim3 grid(unsigned(N1 / 256), unsigned(items));
+  if constexpr (N1 == 16384) {  // only N = 2^20 uses rows of 16384
+    hipLaunchKernelGGL((k_long_cols_inv<N1, 32, SRC>), grid, dim3(256), 0, st, a);
+  } else {
+    switch (a.N2) {
+      case 4: hipLaunchKernelGGL((k_long_cols_inv<N1, 4, SRC>), grid, dim3(256), 0, st, a); break;
+      case 8: hipLaunchKernelGGL((k_long_cols_inv<N1, 8, SRC>), grid, dim3(256), 0, st, a); break;
+      case 16: hipLaunchKernelGGL((k_long_cols_inv<N1, 16, SRC>), grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_long_cols_inv<N1, 32, SRC>), grid, dim3(256), 0, st, a); break;
+    }
   }
+}
+
+// The passes of one window stage at row length N1 (see long_window).
+template <int N1>
+void long_passes(const DevCfg& d, int src, const LongArgs& a, const float* hdet, int64_t items, hipStream_t st) {
+  const dim3 bins_grid(unsigned(N1 / 512), unsigned(items), unsigned(a.N2 / 2 + 1));
+  const dim3 inject_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
+  const dim3 rows_grid(unsigned(items * a.N2));
+  if (src == 2) {
+    hipLaunchKernelGGL((k_long_inject<N1>), inject_grid, dim3(256), 0, st, a, hdet);
+    hipLaunchKernelGGL((k_long_rows<N1, +1>), rows_grid, dim3(N1 / 16), 0, st, a);
+    launch_cols_inv<N1, 2>(a, items, st);
+    return;
+  }
+  if (src == 0) launch_cols_fwd<N1, 0>(a, items, st);
+  else launch_cols_fwd<N1, 1>(a, items, st);
+  if (d.ord_win) {
+    // rows, bins and inverse rows fused per row pair
+    const dim3 pair_grid(unsigned(items * (a.N2 / 2 + 1)));
+    if (src == 0) hipLaunchKernelGGL((k_long_rowpair<N1, double, 0>), pair_grid, dim3(N1 / 16), 0, st, a);
+    else if (d.precision == 0) hipLaunchKernelGGL((k_long_rowpair<N1, float, 1>), pair_grid, dim3(N1 / 16), 0, st, a);
+    else hipLaunchKernelGGL((k_long_rowpair<N1, double, 1>), pair_grid, dim3(N1 / 16), 0, st, a);
+    launch_cols_inv<N1, 0>(a, items, st);
+    return;
+  }
+  hipLaunchKernelGGL((k_long_rows<N1, -1>), rows_grid, dim3(N1 / 16), 0, st, a);
+  if (src == 0) {
+    hipLaunchKernelGGL((k_long_bins<N1, double, 0>), bins_grid, dim3(256), 0, st, a);
+  } else if (d.precision == 0) {
+    hipLaunchKernelGGL((k_long_bins<N1, float, 1>), bins_grid, dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_long_bins<N1, double, 1>), bins_grid, dim3(256), 0, st, a);
+  }
+  hipLaunchKernelGGL((k_long_rows<N1, +1>), rows_grid, dim3(N1 / 16), 0, st, a);
+  launch_cols_inv<N1, 0>(a, items, st);
 }
 
 }  // namespace
 
 namespace gw {
+
+int long_row_length(int NC) { return NC / 8192 <= 32 ? 8192 : 16384; }
 
 // The window stage for N > 32768: SRC 0 whitens strain rows x, SRC 1 is the
 // fused batch (x = background), SRC 2 injects hdet into the background
@@ -567,7 +615,8 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   a.tw1 = c->tw_win;
   a.x = x;
   a.NC = d.N / 2;
-  a.N2 = a.NC / kN1;
+  const int N1 = long_row_length(a.NC);
+  a.N2 = a.NC / N1;
   a.l2n2 = 0;
   while ((1 << a.l2n2) < a.N2) ++a.l2n2;
   const char* tabs = static_cast<const char*>(c->long_tabs);
@@ -577,37 +626,10 @@ gw_status long_window(gw_ctx* c, int src, const WinArgs& w, const float* x, cons
   if (items <= 0) return GW_OK;
   if (items > 65535) return ctx_fail(c, GW_EINVAL, "long windows: at most 65535 (sample, detector) items per call");
   if (!c->long_tabs) return ctx_fail(c, GW_EUNSUPPORTED, "long windows need the binary32 tables");
-  const dim3 bins_grid(unsigned(kN1 / 512), unsigned(items), unsigned(a.N2 / 2 + 1));
-  const dim3 inject_grid(unsigned((a.NC / 2 + 1 + 255) / 256), unsigned(items));
-  const dim3 rows_grid(unsigned(items * a.N2));
-  if (src == 2) {
-    hipLaunchKernelGGL(k_long_inject, inject_grid, dim3(256), 0, st, a, hdet);
-    hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
-    launch_cols_inv<2>(a, items, st);
-    return ctx_check_launch(c, "long inject");
-  }
-  if (src == 0) launch_cols_fwd<0>(a, items, st);
-  else launch_cols_fwd<1>(a, items, st);
-  if (d.ord_win) {
-    // rows, bins and inverse rows fused per row pair
-    const dim3 pair_grid(unsigned(items * (a.N2 / 2 + 1)));
-    if (src == 0) hipLaunchKernelGGL((k_long_rowpair<double, 0>), pair_grid, dim3(kN1 / 16), 0, st, a);
-    else if (d.precision == 0) hipLaunchKernelGGL((k_long_rowpair<float, 1>), pair_grid, dim3(kN1 / 16), 0, st, a);
-    else hipLaunchKernelGGL((k_long_rowpair<double, 1>), pair_grid, dim3(kN1 / 16), 0, st, a);
-    launch_cols_inv<0>(a, items, st);
-    return ctx_check_launch(c, "long window");
-  }
-  hipLaunchKernelGGL((k_long_rows<-1>), rows_grid, dim3(kN1 / 16), 0, st, a);
-  if (src == 0) {
-    hipLaunchKernelGGL((k_long_bins<double, 0>), bins_grid, dim3(256), 0, st, a);
-  } else if (d.precision == 0) {
-    hipLaunchKernelGGL((k_long_bins<float, 1>), bins_grid, dim3(256), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_long_bins<double, 1>), bins_grid, dim3(256), 0, st, a);
-  }
-  hipLaunchKernelGGL((k_long_rows<+1>), rows_grid, dim3(kN1 / 16), 0, st, a);
-  launch_cols_inv<0>(a, items, st);
-  return ctx_check_launch(c, "long window");
+  if (a.N2 < 4 || a.N2 > 32 || a.N2 * N1 != a.NC) return ctx_fail(c, GW_EUNSUPPORTED, "long windows: bad split");
+  if (N1 == 8192) long_passes<8192>(d, src, a, hdet, items, st);
+  else long_passes<16384>(d, src, a, hdet, items, st);
+  return ctx_check_launch(c, src == 2 ? "long inject" : "long window");
 }
 
 }  // namespace gw

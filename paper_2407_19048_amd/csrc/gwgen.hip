@@ -470,12 +470,12 @@ gw_status upload_twiddles(gw_ctx* c, void** dst, int n, int denom) {
 }
 
 // Per-bin tables of the long-window bins pass in the transposed layout of
-// its spectrum (row k mod N2, column k / N2, rows of 16384): one allocation
+// its spectrum (row k mod N2, column k / N2, rows of N1): one allocation
 // of double[NC] k^(1/3), double[NC] ln(k)/3, cpx<float>[NC] exp(-2 pi i k/N).
 // Also the column twiddles W_NC^(m1 k2) at [k2][m1] (c->tw_long), so that a
 // wavefront's threads (consecutive m1) read consecutive entries.
 gw_status upload_long_tables(gw_ctx* c, int NC) {
-  const int N1 = 16384, N2 = NC / N1;
+  const int N1 = long_row_length(NC), N2 = NC / N1;
   std::vector<double> kc(NC), lk(NC);
   std::vector<cpx<float>> tw(NC), twc(NC);
   for (int k = 0; k < NC; ++k) {
@@ -876,8 +876,8 @@ gw_status gw_create(const gw_config* cfg, gw_ctx** out) {
     if (s == GW_OK) s = upload_twiddles<double>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<double>(c, &c->tw_welch, dc.L, dc.L);
   } else {
-    // windows longer than 32768 samples transform rows of 16384 (four-step)
-    const int NCt = NC > 16384 ? 16384 : NC;
+    // windows longer than 32768 samples transform rows of N1 (four-step)
+    const int NCt = NC > 16384 ? long_row_length(NC) : NC;
     s = upload_twiddles<float>(c, &c->tw_win, NCt, NCt);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->twr_win, NC / 2 + 1, dc.N);
     if (s == GW_OK) s = upload_twiddles<float>(c, &c->tw_welch, dc.L, dc.L);

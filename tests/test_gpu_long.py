@@ -1,6 +1,7 @@
 """Windows longer than 32768 samples (four-step transforms through HBM)
-against the oracle: the fused batch for every column length N2 = N/32768
-in {2, 4, 8, 16, 32}, the benchmark's batch of 256 at N = 2^19 (sampled),
+against the oracle: the fused batch for every split NC = N1 x N2 (rows of
+N1 = 8192 with N2 = 4, 8, 16, 32 for N = 2^16 ... 2^19, rows of 16384 with
+N2 = 32 for N = 2^20), the benchmark's batch of 256 at N = 2^19 (sampled),
 sine-Gaussian bursts, and the inject and whiten steps (whitened relative L2
 per window <= 1e-5)."""
 
@@ -51,7 +52,8 @@ def test_long_fused_batch_matches_oracle(T):
     out = torch.empty((B, 3, N), dtype=torch.float32, device=DEV)
     st = torch.zeros(B, dtype=torch.int32, device=DEV)
     ws = gen.alloc_workspace(B)
-    _say("long fused T=%g N=%d N2=%d" % (T, N, N // 32768))
+    N1 = 8192 if N <= (1 << 19) else 16384
+    _say("long fused T=%g N=%d N1=%d N2=%d" % (T, N, N1, N // (2 * N1)))
     gen.generate_batch(5, 1, B, torch.from_numpy(bg_np).to(DEV), out, ws, status=st)
     torch.cuda.synchronize()
     params, offs = gen.workspace_views(ws, B)
