@@ -551,6 +551,15 @@ def main():
     welch_tflops = welch_flops / (welch_ms * 1e-3) / 1e12
     from paper_2407_19048_amd.profiling import measured_traffic
     traffic = measured_traffic("k_welch", "paper_scale_B%d" % B)
+    # the fused window kernel (second kernel of the step), timed by the
+    # autotuner with events on its stream: per (sample, detector) it reads the
+    # N-sample window and the Fw-bin PSD and writes N samples
+    win_ms = tune["window_ord%d" % tuned["ord_window"]]
+    win_bytes = B * n_det * (2 * z["N"] + z["Fw"]) * 4
+    win_gbs = win_bytes / (win_ms * 1e-3) / 1e9
+    window_rec = {"kernel": "k_window", "ms_per_launch": round(win_ms, 4), "bytes_per_launch": win_bytes,
+                  "achieved_gbs": round(win_gbs, 1), "hbm_frac": round(win_gbs / HBM_PEAK_GBS, 4),
+                  "traffic": measured_traffic("k_window", "paper_scale_B%d" % B)}
 
     # device-to-device copy of 1 GiB (or --copy-probe-gib): the bandwidth a
     # plain streaming kernel reaches on this part, timed with events on the
@@ -570,6 +579,7 @@ def main():
     log("copy probe: %d bytes read + written per copy, %.0f GB/s" % (4 * n, copy_gbs))
     del src, dst
 
+    window_rec["frac_of_copy"] = round(win_gbs / copy_gbs, 4)
     # whole step, algorithmic bytes per sample: D (P + N) reads + D N writes
     step_bytes = B * n_det * ((z["P"] + z["N"]) + z["N"]) * 4
     step_gbs = step_bytes / (elapsed / K) / 1e9
@@ -644,6 +654,7 @@ def main():
             "step_frac_of_copy": round(step_gbs / copy_gbs, 4),
             "bytes_per_launch": welch_bytes,
             "traffic": traffic,
+            "window_kernel": window_rec,
         },
         "cpu_baseline": cpu,
         "surrogate": surrogate,

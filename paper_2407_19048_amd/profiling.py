@@ -6,6 +6,12 @@
         per-dispatch means of every counter of a --pmc run for the matching kernels (markdown)
     python -m paper_2407_19048_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL VARIANT GRID WORKLOAD COPY_GIB "COMMAND"
         HBM traffic record (JSON in profiles/) as described below
+    python -m paper_2407_19048_amd.profiling trace TRACE_CSV KERNEL_SUBSTR[,...] TITLE "COMMAND" [GRID,...]
+        per (kernel, grid, workgroup) dispatch count, average and median duration (markdown) from the
+        kernel trace of a --kernel-trace run, for the kernels matching any substring (and grid, if given)
+    python -m paper_2407_19048_amd.profiling valu COUNTER_DIR KERNEL_SUBSTR[,KERNEL_SUBSTR...] TITLE "COMMAND"
+        VALU issue, LDS bank-conflict and wait shares per kernel (markdown) from a --pmc run with
+        SQ_INSTS_VALU SQ_WAVES SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_WAIT_ANY SQ_WAVE_CYCLES
 
 HBM traffic of a kernel from two rocprofv3 counter runs.
 
@@ -137,7 +143,7 @@ def stats_table(stats_csv, title, command, top=14):
            "| kernel | calls | average | total | share |", "|---|---|---|---|---|"]
     for r in rows[:top]:
         out.append("| `%s` | %s | %.4f ms | %.3f ms | %.2f %% |"
-                   % (r[name], r[calls], float(r[avg]) / 1e6, float(r[total]) / 1e6, 100.0 * float(r[total]) / grand))
+                   % (short_name(r[name]), r[calls], float(r[avg]) / 1e6, float(r[total]) / 1e6, 100.0 * float(r[total]) / grand))
     return "\n".join(out) + "\n"
 
 
@@ -161,12 +167,117 @@ def counters_table(counter_dir, kernel_substr, title, command):
     return "\n".join(out) + "\n"
 
 
+def short_name(name):
+    """Demangled kernel name without 'void', anonymous-namespace qualifiers
+    and the argument list: k_welch<float, double, 4096, 0, 3>."""
+    n = name.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
+def trace_table(trace_csv, kernel_substrs, title, command, grids=None):
+    """Markdown table per (kernel, grid, workgroup size) from a rocprofv3
+    kernel trace: dispatches, average and median duration, sorted by total
+    time.  kernel_substrs: comma-separated substrings (any matches); grids:
+    optional comma-separated grid sizes in work-items."""
+    subs = [k for k in kernel_substrs.split(",") if k]
+    keep = {int(g) for g in grids.split(",")} if grids else None
+    with open(trace_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    acc = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        if not any(k in name for k in subs):
+            continue
+        grid = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1) or 1) * int(r.get("Grid_Size_Z", 1) or 1)
+        if keep is not None and grid not in keep:
+            continue
+        wg = int(r["Workgroup_Size_X"]) * int(r.get("Workgroup_Size_Y", 1) or 1) * int(r.get("Workgroup_Size_Z", 1) or 1)
+        acc.setdefault((name, grid, wg), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+    if not acc:
+        raise ValueError("no matching dispatch in %s" % trace_csv)
+    out = ["# %s" % title, "", "Command (one MI355X):", "", "    %s" % command, "",
+           "Per (kernel, grid, workgroup) from `%s`:" % os.path.basename(trace_csv), "",
+           "| kernel | grid (work-items) | workgroup | dispatches | average | median | total |",
+           "|---|---|---|---|---|---|---|"]
+    for (name, grid, wg), ms in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        ms_s = sorted(ms)
+        med = ms_s[len(ms_s) // 2] if len(ms_s) % 2 else 0.5 * (ms_s[len(ms_s) // 2 - 1] + ms_s[len(ms_s) // 2])
+        out.append("| `%s` | %d | %d | %d | %.4f ms | %.4f ms | %.3f ms |"
+                   % (short_name(name), grid, wg, len(ms), sum(ms) / len(ms), med, sum(ms)))
+    return "\n".join(out) + "\n"
+
+
+# MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a 16-lane
+# SIMD for 4 cycles (unpacked binary32 or binary64) at the 2.4 GHz peak clock
+N_SIMD, CYCLES_PER_VALU, CLOCK_HZ = 1024, 4, 2.4e9
+
+
+def valu_table(counter_dir, kernel_substrs, title, command):
+    """Markdown table per (kernel, grid): waves, VALU instructions per wave,
+    mean dispatch duration, VALU issue estimate 4 SQ_INSTS_VALU / (1024 SIMDs
+    x duration x 2.4 GHz), LDS conflict share SQ_LDS_BANK_CONFLICT /
+    SQ_LDS_IDX_ACTIVE and wait share SQ_WAIT_ANY / SQ_WAVE_CYCLES.  Durations
+    come from the dispatch timestamps of the counter run."""
+    subs = [k for k in kernel_substrs.split(",") if k]
+    rows = [r for r in _rows(counter_dir) if any(k in r["Kernel_Name"] for k in subs)]
+    if not rows:
+        raise ValueError("no dispatch of %s in %s" % (kernel_substrs, counter_dir))
+    acc, dur = {}, {}
+    for r in rows:
+        key = (r["Kernel_Name"], int(r["Grid_Size"]))
+        acc.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            dur.setdefault(key, {})[r.get("Dispatch_Id", r.get("Correlation_Id"))] = (
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+
+    def mean(v, c):
+        return sum(v[c]) / len(v[c]) if c in v and v[c] else float("nan")
+
+    out = ["# %s" % title, "", "Command (one MI355X):", "", "    %s" % command, "",
+           "Per dispatch (mean over dispatches; duration from the dispatch timestamps of the counter run). "
+           "A wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles (unpacked binary32 or binary64), "
+           "so the VALU issue estimate is 4 x SQ_INSTS_VALU / (1024 SIMDs x duration x 2.4 GHz): exact at the "
+           "2.4 GHz peak engine clock with every instruction taking 4 cycles; a lower clock raises the true "
+           "fraction, and a value near or just above 100 % means the kernel is at the issue limit. LDS conflict "
+           "share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE; wait share = SQ_WAIT_ANY / SQ_WAVE_CYCLES (waves "
+           "stalled on s_waitcnt).", "",
+           "| kernel | grid | dispatches | waves | VALU instructions per wave | duration | VALU issue (estimate) "
+           "| LDS conflict share | wait share |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for (k, g), v in sorted(acc.items(), key=lambda kv: -mean(kv[1], "SQ_INSTS_VALU")):
+        waves, valu = mean(v, "SQ_WAVES"), mean(v, "SQ_INSTS_VALU")
+        ds = list(dur.get((k, g), {}).values())
+        d = sum(ds) / len(ds) if ds else float("nan")
+        issue = CYCLES_PER_VALU * valu / (N_SIMD * d * CLOCK_HZ) if ds else float("nan")
+        conf = mean(v, "SQ_LDS_BANK_CONFLICT") / mean(v, "SQ_LDS_IDX_ACTIVE") if mean(v, "SQ_LDS_IDX_ACTIVE") else 0.0
+        wait = mean(v, "SQ_WAIT_ANY") / mean(v, "SQ_WAVE_CYCLES") if mean(v, "SQ_WAVE_CYCLES") else float("nan")
+        n = max(len(x) for x in v.values())
+        out.append("| `%s` | %d | %d | %.0f | %.0f | %.4f ms | %.1f %% | %.1f %% | %.1f %% |"
+                   % (short_name(k), g, n, waves, valu / waves if waves else float("nan"), d * 1e3, 100 * issue,
+                      100 * conf, 100 * wait))
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
     if len(a) == 4 and a[0] == "stats":
         sys.stdout.write(stats_table(a[1], a[2], a[3]))
     elif len(a) == 5 and a[0] == "counters":
         sys.stdout.write(counters_table(a[1], a[2], a[3], a[4]))
+    elif len(a) in (5, 6) and a[0] == "trace":
+        sys.stdout.write(trace_table(a[1], a[2], a[3], a[4], a[5] if len(a) == 6 else None))
+    elif len(a) == 5 and a[0] == "valu":
+        sys.stdout.write(valu_table(a[1], a[2], a[3], a[4]))
     elif len(a) == 9 and a[0] == "traffic":
         print(json.dumps(summarise(a[1], a[2], a[3], a[4], int(a[5]), a[6], float(a[7]), a[8]), indent=1))
     else:
