@@ -6,9 +6,10 @@
         per-dispatch means of every counter of a --pmc run for the matching kernels (markdown)
     python -m paper_2407_19048_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL VARIANT GRID WORKLOAD COPY_GIB "COMMAND"
         HBM traffic record (JSON in profiles/) as described below
-    python -m paper_2407_19048_amd.profiling trace TRACE_CSV KERNEL_SUBSTR[,...] TITLE "COMMAND" [GRID,...]
+    python -m paper_2407_19048_amd.profiling trace TRACE_CSV FILTER[,FILTER...] TITLE "COMMAND"
         per (kernel, grid, workgroup) dispatch count, average and median duration (markdown) from the
-        kernel trace of a --kernel-trace run, for the kernels matching any substring (and grid, if given)
+        kernel trace of a --kernel-trace run, for the dispatches matching any FILTER: a kernel-name
+        substring, optionally followed by @GRID[|GRID...] (total work-items) to keep only those grids
     python -m paper_2407_19048_amd.profiling valu COUNTER_DIR KERNEL_SUBSTR[,KERNEL_SUBSTR...] TITLE "COMMAND"
         VALU issue, LDS bank-conflict and wait shares per kernel (markdown) from a --pmc run with
         SQ_INSTS_VALU SQ_WAVES SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_WAIT_ANY SQ_WAVE_CYCLES
@@ -184,22 +185,24 @@ def short_name(name):
     return n
 
 
-def trace_table(trace_csv, kernel_substrs, title, command, grids=None):
+def trace_table(trace_csv, filters, title, command):
     """Markdown table per (kernel, grid, workgroup size) from a rocprofv3
     kernel trace: dispatches, average and median duration, sorted by total
-    time.  kernel_substrs: comma-separated substrings (any matches); grids:
-    optional comma-separated grid sizes in work-items."""
-    subs = [k for k in kernel_substrs.split(",") if k]
-    keep = {int(g) for g in grids.split(",")} if grids else None
+    time.  filters: comma-separated kernel-name substrings, each optionally
+    with @GRID[|GRID...] (grid sizes in work-items) to keep only those."""
+    flt = []
+    for f in filters.split(","):
+        if not f:
+            continue
+        sub, _, grids = f.partition("@")
+        flt.append((sub, {int(g) for g in grids.split("|")} if grids else None))
     with open(trace_csv) as fh:
         rows = list(csv.DictReader(fh))
     acc = {}
     for r in rows:
         name = r["Kernel_Name"]
-        if not any(k in name for k in subs):
-            continue
         grid = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1) or 1) * int(r.get("Grid_Size_Z", 1) or 1)
-        if keep is not None and grid not in keep:
+        if not any(sub in name and (keep is None or grid in keep) for sub, keep in flt):
             continue
         wg = int(r["Workgroup_Size_X"]) * int(r.get("Workgroup_Size_Y", 1) or 1) * int(r.get("Workgroup_Size_Z", 1) or 1)
         acc.setdefault((name, grid, wg), []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
@@ -274,8 +277,8 @@ if __name__ == "__main__":
         sys.stdout.write(stats_table(a[1], a[2], a[3]))
     elif len(a) == 5 and a[0] == "counters":
         sys.stdout.write(counters_table(a[1], a[2], a[3], a[4]))
-    elif len(a) in (5, 6) and a[0] == "trace":
-        sys.stdout.write(trace_table(a[1], a[2], a[3], a[4], a[5] if len(a) == 6 else None))
+    elif len(a) == 5 and a[0] == "trace":
+        sys.stdout.write(trace_table(a[1], a[2], a[3], a[4]))
     elif len(a) == 5 and a[0] == "valu":
         sys.stdout.write(valu_table(a[1], a[2], a[3], a[4]))
     elif len(a) == 9 and a[0] == "traffic":

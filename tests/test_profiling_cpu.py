@@ -49,8 +49,9 @@ def test_trace_table_groups_by_grid(tmp_path):
     assert lines[0] == "| `k_a<1>` | 1024 | 256 | 1 | 9.0000 ms | 9.0000 ms | 9.000 ms |"
     assert lines[1] == "| `k_a<1>` | 512 | 256 | 3 | 2.0000 ms | 2.0000 ms | 6.000 ms |"
     assert len(lines) == 2
-    t = profiling.trace_table(str(p), "k_a,k_b", "T", "cmd", grids="512,64")
-    assert [l.split("|")[1].strip() for l in t.splitlines() if l.startswith("| `")] == ["`k_a<1>`", "`k_b`"]
+    t = profiling.trace_table(str(p), "k_a@512|7,k_b", "T", "cmd")
+    assert [l.split("|")[1:3] for l in t.splitlines() if l.startswith("| `")] == [
+        [" `k_a<1>` ", " 512 "], [" `k_b` ", " 64 "]]
 
 
 def test_stats_table_sorted_by_total(tmp_path):
