@@ -339,16 +339,17 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     }
     return q;
   };
-  PairIn nxt = fetch(t);
-
-  // pairs (k, NC - k) for k in [0, NC/2]
-#pragma unroll 1
-  for (int i = 0; i <= 8; ++i) {
-    const int k = t + NT * i;
-    if (k > NC / 2) break;
+  // the pair's spectrum values (k, NC - k) from LDS
+  auto load_pair = [&](int k, cpx<T>& A, cpx<T>& Bm) {
+    if constexpr (SRC != 2) {
+      const int ia = lpad<T>(k), ib = lpad<T>((NC - k) & (NC - 1));
+      A = {sre[ia], sim[ia]};
+      Bm = {sre[ib], sim[ib]};
+    }
+  };
+  // unpack, signal, gain and repack of the pair: zk, zm go to bins k, NC - k
+  auto pair_out = [&](const PairIn& cur, int k, cpx<T> A, cpx<T> Bm, cpx<T>& zk, cpx<T>& zm) {
     const int km = NC - k;
-    const PairIn cur = nxt;
-    nxt = fetch(k + NT);
     const cpx<T> W = cur.W;
     cpx<T> Yk, Ym;
     if constexpr (SRC == 2) {
@@ -356,9 +357,6 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       Ym = {T(cur.g[2]), T(cur.g[3])};
       if (k == 0) { Yk.y = T(0); Ym.y = T(0); }  // irfft ignores Im at DC and Nyquist
     } else {
-      const int ia = lpad<T>(k), ib = lpad<T>(km & (NC - 1));
-      const cpx<T> A = {sre[ia], sim[ia]};
-      const cpx<T> Bm = {sre[ib], sim[ib]};
       const cpx<T> s = cadd(A, cconj(Bm));
       const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
       cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
@@ -388,14 +386,44 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     // inverse packing: Z'_k = p + i q, Z'_{NC-k} = conj(p) + i conj(q)
     const cpx<T> p = cscale(cadd(Yk, cconj(Ym)), T(0.5));
     const cpx<T> q = twmul<+1>(cscale(csub(Yk, cconj(Ym)), T(0.5)), W);
+    zk = {p.x - q.y, p.y + q.x};
+    zm = {p.x + q.y, -p.y + q.x};
+  };
+  auto store_pair = [&](int k, cpx<T> zk, cpx<T> zm) {
+    const int km = NC - k;
     const int ia = lpad<T>(k);
-    sre[ia] = p.x - q.y;
-    sim[ia] = p.y + q.x;
+    sre[ia] = zk.x;
+    sim[ia] = zk.y;
     if (k != 0 && km != k) {
       const int ib = lpad<T>(km);
-      sre[ib] = p.x + q.y;
-      sim[ib] = -p.y + q.x;
+      sre[ib] = zm.x;
+      sim[ib] = zm.y;
     }
+  };
+
+  // pairs (k, NC - k) for k = t + NT i in [0, NC/2] (NC/2 = 8 NT): two per
+  // loop trip, whose LDS reads are issued together and whose arithmetic
+  // chains interleave; the last one (k = NC/2) belongs to thread 0 alone
+  PairIn n0 = fetch(t), n1 = fetch(t + NT);
+#pragma unroll 1
+  for (int i = 0; i < 8; i += 2) {
+    const int k0 = t + NT * i, k1 = k0 + NT;
+    const PairIn c0 = n0, c1 = n1;
+    n0 = fetch(k0 + 2 * NT);
+    n1 = fetch(k1 + 2 * NT);
+    cpx<T> A0 = {}, B0 = {}, A1 = {}, B1 = {}, z0k, z0m, z1k, z1m;
+    load_pair(k0, A0, B0);
+    load_pair(k1, A1, B1);
+    pair_out(c0, k0, A0, B0, z0k, z0m);
+    pair_out(c1, k1, A1, B1, z1k, z1m);
+    store_pair(k0, z0k, z0m);
+    store_pair(k1, z1k, z1m);
+  }
+  if (t == 0) {  // n0 = fetch(NC/2)
+    cpx<T> A = {}, Bm = {}, zk, zm;
+    load_pair(NC / 2, A, Bm);
+    pair_out(n0, NC / 2, A, Bm, zk, zm);
+    store_pair(NC / 2, zk, zm);
   }
   lds_barrier();
   block_fft<T, NC, +1, true, ORD>(v, sre, sim, fresh_lane(t), PowTwiddle<T, NC, ORD>{opaque(twtab)});
