@@ -6,7 +6,7 @@
         per-dispatch means of every counter of a --pmc run for the matching kernels (markdown)
     python -m paper_2407_19048_amd.profiling traffic FETCH_DIR WRITE_DIR KERNEL VARIANT GRID WORKLOAD COPY_GIB "COMMAND"
         HBM traffic record (JSON in profiles/) as described below
-    python -m paper_2407_19048_amd.profiling trace TRACE_CSV FILTER[,FILTER...] TITLE "COMMAND"
+    python -m paper_2407_19048_amd.profiling trace TRACE_CSV "FILTER[;FILTER...]" TITLE "COMMAND"
         per (kernel, grid, workgroup) dispatch count, average and median duration (markdown) from the
         kernel trace of a --kernel-trace run, for the dispatches matching any FILTER: a kernel-name
         substring, optionally followed by @GRID[|GRID...] (total work-items) to keep only those grids
@@ -188,10 +188,11 @@ def short_name(name):
 def trace_table(trace_csv, filters, title, command):
     """Markdown table per (kernel, grid, workgroup size) from a rocprofv3
     kernel trace: dispatches, average and median duration, sorted by total
-    time.  filters: comma-separated kernel-name substrings, each optionally
-    with @GRID[|GRID...] (grid sizes in work-items) to keep only those."""
+    time.  filters: kernel-name substrings separated by ';' (names contain
+    commas), each optionally with @GRID[|GRID...] (grid sizes in work-items)
+    to keep only those."""
     flt = []
-    for f in filters.split(","):
+    for f in filters.split(";"):
         if not f:
             continue
         sub, _, grids = f.partition("@")

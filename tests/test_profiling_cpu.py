@@ -44,14 +44,19 @@ def test_trace_table_groups_by_grid(tmp_path):
             w.writerow(["void k_a<1>(Args)", t0, t1, 512, 1, 1, 256, 1, 1])
         w.writerow(["void k_a<1>(Args)", 0, 9000000, 1024, 1, 1, 256, 1, 1])
         w.writerow(["void k_b(Args)", 0, 5000000, 64, 1, 1, 64, 1, 1])
+        w.writerow(["void k_c<float, 4>(Args)", 0, 7000000, 64, 1, 1, 64, 1, 1])
+        w.writerow(["void k_c<float, 1>(Args)", 0, 7000000, 64, 1, 1, 64, 1, 1])
     t = profiling.trace_table(str(p), "k_a", "T", "cmd")
     lines = [l for l in t.splitlines() if l.startswith("| `")]
     assert lines[0] == "| `k_a<1>` | 1024 | 256 | 1 | 9.0000 ms | 9.0000 ms | 9.000 ms |"
     assert lines[1] == "| `k_a<1>` | 512 | 256 | 3 | 2.0000 ms | 2.0000 ms | 6.000 ms |"
     assert len(lines) == 2
-    t = profiling.trace_table(str(p), "k_a@512|7,k_b", "T", "cmd")
+    t = profiling.trace_table(str(p), "k_a@512|7;k_b", "T", "cmd")
     assert [l.split("|")[1:3] for l in t.splitlines() if l.startswith("| `")] == [
         [" `k_a<1>` ", " 512 "], [" `k_b` ", " 64 "]]
+    # substrings with commas select template arguments
+    t = profiling.trace_table(str(p), "k_c<float, 4", "T", "cmd")
+    assert [l.split("|")[1].strip() for l in t.splitlines() if l.startswith("| `")] == ["`k_c<float, 4>`"]
 
 
 def test_stats_table_sorted_by_total(tmp_path):
