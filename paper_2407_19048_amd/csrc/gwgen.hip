@@ -519,8 +519,10 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   if (!integral(Nd) || !integral(Pd) || !integral(Ld) || !integral(Sd))
     return bad("t_window, psd_length, fftlen and overlap must be whole numbers of samples");
   const int64_t N = std::llround(Nd), P = std::llround(Pd), L = std::llround(Ld), S = std::llround(Sd);
-  if (!is_pow2(N) || N < 2048 || N > (int64_t(1) << 20))
-    return bad("N = t_window*fs must be a power of two in [2048, 2^20]");
+  // the window transforms run NC = N/2 in {2048, ..., 16384} points in one
+  // workgroup (four-step beyond): shorter windows have no kernel
+  if (!is_pow2(N) || N < 4096 || N > (int64_t(1) << 20))
+    return bad("N = t_window*fs must be a power of two in [4096, 2^20]");
   if (N > 32768 && g->precision == 2) return GW_EUNSUPPORTED;
   if (!is_pow2(L) || L < 2048 || L > 4096) return bad("L = fftlen*fs must be 2048 or 4096");
   if (S * 2 != L) return bad("overlap must be half of fftlen (stride L/2)");
