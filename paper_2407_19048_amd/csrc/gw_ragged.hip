@@ -828,7 +828,7 @@ gw_status gw_ragged_autotune(gw_ragged* r, const float* const* bg, const int64_t
     r->win_mode = saved[4];
     r->welch_mode = saved[5];
   }
-  (void)hipStreamSynchronize(st);
+  if (hipStreamSynchronize(st) != hipSuccess && s == GW_OK) s = rfail(r, GW_EHIP, "hipStreamSynchronize");
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);

@@ -1245,7 +1245,7 @@ gw_status gw_autotune(gw_ctx* c, int64_t B, const float* bg, int64_t L_bg, float
     c->dc.occ_welch = saved[1];
     c->dc.ord_win = saved[2];
   }
-  (void)hipStreamSynchronize(st);
+  if (hipStreamSynchronize(st) != hipSuccess && s == GW_OK) s = fail(c, GW_EHIP, "hipStreamSynchronize");
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
