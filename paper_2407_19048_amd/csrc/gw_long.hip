@@ -44,7 +44,7 @@ __device__ __forceinline__ void dft_small(cpx<T>* a) {
   else if constexpr (R == 8) dft8<DIR>(a);
   else if constexpr (R == 16) dft16<DIR>(a);
   else {
-    static_assert(R == 32, "N2 in {2, 4, 8, 16, 32}");
+    static_assert(R == 32, "N2 in {4, 8, 16, 32}");
     cpx<T> e[16], o[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {

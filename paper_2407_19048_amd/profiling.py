@@ -20,8 +20,9 @@ FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are taken in separate runs of
 the same command, which also copies a device buffer of known size (bench.py
 --copy-probe-gib).  Each counter is scaled by the factor that makes it read
 the known size on that copy, so the result is in bytes moved between the
-chip and HBM.  The summary is stored with a hash of the kernel sources; the
-benchmark reports it only while the hash still matches.
+chip and HBM.  The summary is stored with a hash of the sources of the
+kernel's translation unit (KERNEL_SOURCES); the benchmark reports it only
+while the hash still matches.
 
 VARIANT is a substring of the demangled kernel name that selects the
 instantiation the benchmark times (other variants, e.g. the autotuner's
@@ -39,12 +40,26 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_2407_19048_amd", "csrc")
 
 
-def kernel_source_hash():
+# Sources of the translation unit that defines each profiled kernel (the
+# .hip file and every header it includes); a traffic record stays valid while
+# these are unchanged.  Kernels not listed hash every source.
+_PLAIN_TU = ("paper_2407_19048_amd/csrc/gwgen.hip", "paper_2407_19048_amd/csrc/gw_fft.hpp",
+             "paper_2407_19048_amd/csrc/gw_physics.hpp", "paper_2407_19048_amd/csrc/gw_internal.hpp",
+             "paper_2407_19048_amd/csrc/gw_items.hpp", "include/gwgen.h")
+KERNEL_SOURCES = {"k_welch": _PLAIN_TU, "k_window": _PLAIN_TU}
+
+
+def _all_sources():
+    return tuple(sorted(os.path.join("paper_2407_19048_amd", "csrc", f) for f in os.listdir(SRC)
+                        if f.endswith((".hip", ".hpp")))) + ("include/gwgen.h",)
+
+
+def kernel_source_hash(kernel=None):
     h = hashlib.sha256()
-    for f in sorted(os.listdir(SRC)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(SRC, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES[kernel] if kernel in KERNEL_SOURCES else _all_sources():
+        h.update(f.encode())
+        with open(os.path.join(os.path.dirname(os.path.dirname(SRC)), f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -59,7 +74,7 @@ def measured_traffic(kernel, workload):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -101,7 +116,8 @@ def summarise(fetch_dir, write_dir, kernel, variant, grid, workload, copy_gib, c
         "variant": variant,
         "grid": int(grid),
         "workload": workload,
-        "source_hash": kernel_source_hash(),
+        "source_hash": kernel_source_hash(kernel),
+        "sources": list(KERNEL_SOURCES.get(kernel, ("every kernel source",))),
         "dispatches": [len(f), len(w)],
         "fetch_kib_per_dispatch": round(f_kib, 3),
         "write_kib_per_dispatch": round(w_kib, 3),

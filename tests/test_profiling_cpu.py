@@ -121,5 +121,13 @@ def test_traffic_record_scaled_by_copy_probe(tmp_path, monkeypatch):
         assert json.load(fh)["hbm_bytes_per_launch"] == rec["hbm_bytes_per_launch"]
     # the stored record counts only while the kernel sources are unchanged
     assert profiling.measured_traffic("k_welch", "wl") == rec["hbm_bytes_per_launch"]
-    monkeypatch.setattr(profiling, "kernel_source_hash", lambda: "changed")
+    monkeypatch.setattr(profiling, "kernel_source_hash", lambda kernel=None: "changed")
     assert profiling.measured_traffic("k_welch", "wl") is None
+
+
+def test_source_hash_covers_the_kernels_translation_unit():
+    # the plain kernels' record depends on their translation unit only
+    assert "paper_2407_19048_amd/csrc/gwgen.hip" in profiling.KERNEL_SOURCES["k_welch"]
+    assert not any("gw_long" in f for f in profiling.KERNEL_SOURCES["k_window"])
+    assert profiling.kernel_source_hash("k_welch") == profiling.kernel_source_hash("k_window")
+    assert profiling.kernel_source_hash("k_other") != profiling.kernel_source_hash("k_welch")
