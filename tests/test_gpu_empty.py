@@ -1,0 +1,82 @@
+"""Empty batches (B = 0) through the C ABI: every batch entry point returns
+GW_OK without launching anything or touching its other arguments, which may
+be empty tensors; the calls that need a batch (graph capture, autotuning, an
+uneven-batch handle) reject B = 0 with GW_EINVAL."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2407_19048_amd import gwgen, inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    cfg = inputs.config("paper_scale")
+    gen = gwgen.Generator(cfg)
+    bg = torch.from_numpy(inputs.background(3, 1 << 19, cfg["fs"], seed=1)).to(DEV)
+    return cfg, gen, bg
+
+
+def _e(*shape, dtype=torch.float32):
+    return torch.empty(shape, dtype=dtype, device=DEV)
+
+
+def test_steps_with_empty_batch(setup):
+    cfg, gen, bg = setup
+    z = gen.sizes
+    _say("six steps, B = 0")
+    params, offs = _e(12, 0, dtype=torch.float64), _e(0, dtype=torch.int64)
+    gen.sample_params(1, 0, 0, bg.shape[1], params, offs)
+    hp, hc = _e(0, z["F"], dtype=torch.complex64), _e(0, z["F"], dtype=torch.complex64)
+    gen.gen_fd_waveform(params, hp, hc)
+    hdet = _e(0, 3, z["F"], dtype=torch.complex64)
+    gen.project_detectors(params, hp, hc, hdet)
+    strain = _e(0, 3, z["N"])
+    gen.inject(bg, offs, hdet, strain)
+    psd = _e(0, 3, z["Fw"])
+    gen.welch_psd(bg, offs, psd)
+    gen.whiten(strain, psd, _e(0, 3, z["N"]), _e(0, dtype=torch.int32))
+    torch.cuda.synchronize()
+
+
+def test_batches_with_empty_batch(setup):
+    cfg, gen, bg = setup
+    z = gen.sizes
+    ws = gen.alloc_workspace(0)
+    assert 0 <= gen.workspace_size(0) <= 4096  # at most the graph's batch counter
+    # a sentinel next to the (empty) outputs must stay untouched
+    sentinel = torch.full((1024,), 7.0, device=DEV)
+    _say("fused, view-pair, oversampled, per-run and allocation-free batches, B = 0")
+    gen.generate_batch(1, 0, 0, bg, _e(0, 3, z["N"]), ws, _e(12, 0), _e(0, dtype=torch.int32))
+    gen.generate_batch_pairs(1, 0, 0, bg, _e(0, 3, z["N"]), _e(0, 3, z["N"]), ws)
+    gen.generate_batch_oversampled(1, 0, 0, 4, bg, _e(0, 3, z["N"]), ws)
+    filt = torch.ones((3, z["F"]), dtype=torch.float32, device=DEV)
+    gen.generate_batch_runpsd(1, 0, 0, bg, filt, 2048, _e(0, 3, z["N"] - 4096), ws)
+    gen.generate_batch_noalloc(1, 0, 0, bg, _e(0, 3, z["N"]))
+    torch.cuda.synchronize()
+    assert bool((sentinel == 7.0).all())
+
+
+def test_calls_that_need_a_batch_reject_it(setup):
+    cfg, gen, bg = setup
+    z = gen.sizes
+    ws = gen.alloc_workspace(0)
+    with pytest.raises(gwgen.GWError):
+        gen.graph(1, 0, 0, bg, _e(0, 3, z["N"]), ws)
+    with pytest.raises(gwgen.GWError):
+        gen.autotune(0, bg, _e(0, 3, z["N"]), ws)
+    with pytest.raises(gwgen.GWError):
+        gwgen.Ragged(inputs.ragged_classes(), np.zeros(0, dtype=np.int32))
