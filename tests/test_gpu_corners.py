@@ -4,7 +4,8 @@ extreme regions, where the waveform's branches change: heavy systems with
 near-extremal aligned or anti-aligned spins (merger-ringdown in band, the
 largest spin corrections), systems so heavy that the signal ends below
 f_min (no bin in band) or a few hertz above it, light unequal-mass systems whose inspiral runs past
-Nyquist, distant (weak) signals, and the same corners with TaylorF2.
+Nyquist, distant (weak) signals, the same corners with TaylorF2, and
+sine-Gaussian bursts near Nyquist, at the low end and loud.
 Whitened strain per window within 1e-5 relative L2 of the oracle."""
 
 import sys
@@ -32,6 +33,11 @@ CORNERS = {
     "distant": dict(dl=(20000.0, 30000.0)),
     "taylorf2_heavy_aligned": dict(approximant=0, mc=(80.0, 85.0), q=(0.95, 1.0), chi=(0.9, 0.99)),
     "taylorf2_light_unequal": dict(approximant=0, mc=(0.5, 0.6), q=(0.1, 0.15), chi=(-0.9, -0.8)),
+    # sine-Gaussian bursts: centred near Nyquist and broad (the Gaussian runs
+    # past fs/2), centred at the low end and narrow, and at the upper hrss
+    "burst_near_nyquist_broad": dict(approximant=2, f0=(1000.0, 1020.0), quality=(3.0, 3.2), hrss=(1e-22, 2e-22)),
+    "burst_low_narrow": dict(approximant=2, f0=(32.0, 33.0), quality=(28.0, 30.0), hrss=(1e-22, 2e-22)),
+    "burst_loud": dict(approximant=2, f0=(100.0, 200.0), quality=(8.0, 10.0), hrss=(5e-21, 1e-20)),
 }
 
 _BG = {}
@@ -90,5 +96,5 @@ def test_prior_corner_matches_oracle(corner):
     cut = (st_bits & gwgen.STATUS_CUT_AT_NYQUIST) != 0
     if "light" in corner:
         assert np.all(cut)
-    elif corner != "distant":  # the distant corner keeps the full mass range
+    elif corner != "distant" and not corner.startswith("burst"):  # those keep wide ranges
         assert not np.any(cut)
