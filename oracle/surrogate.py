@@ -31,7 +31,10 @@ Readings:
     interpolation between nodes in u; A = A_N(f_k) * ratio;
     Psi = P_N(f_k) + dpsi - phi_c - pi/4; zero outside f_min <= f_k < f_cut.
   * Mismatch: <a|b> = 4 df Re sum_{kept} a_k conj(b_k) / S_k over
-    f_min <= f_k < f_cut, 0 < k < N/2;  mm = 1 - <a|b>/sqrt(<a|a><b|b>).
+    f_min <= f_k < f_cut, 0 < k < N/2;  mm = 1 - <a|b>/sqrt(<a|a><b|b>)
+    (strict: at the drawn t_c and phi_c).  Reported beside it, the same
+    quantity maximised over a time shift and a phase offset of one
+    waveform (mismatch_maximised).
 
   * Reduced basis: the leading right singular vectors of the mean-removed
     target rows, each with its largest-magnitude component made positive
@@ -215,6 +218,44 @@ def mismatch(a, b, S, df, kept):
     if aa <= 0.0 or bb <= 0.0:
         return 0.0
     return 1.0 - ab / math.sqrt(aa * bb)
+
+
+def overlap_vs_shift(a, b, S, kept, tau):
+    """c(tau) = sum over the kept bins of a_k conj(b_k) / S_k e^{2 pi i k tau}:
+    the complex overlap of a with b delayed by tau window lengths (b_k
+    e^{-2 pi i f_k t}, f_k = k / T, tau = t / T), up to the factor 4 df.
+    Its real part is the overlap at coalescence phase 0; a phase offset phi
+    multiplies it by e^{i phi}."""
+    k = np.nonzero(kept)[0]
+    z = a[k] * np.conj(b[k]) / S[k]
+    return complex(np.sum(z * np.exp(2j * math.pi * k * tau)))
+
+
+def mismatch_maximised(a, b, S, df, kept, n_grid=1 << 18):
+    """1 - max over a time shift and a phase of the normalised overlap: the
+    maximum over the phase of Re(e^{i phi} c(tau)) is |c(tau)|; the maximum
+    over tau in [0, 1) (c has period one window) is taken as the best point of
+    a grid of n_grid shifts (an inverse DFT of the zero-padded products)
+    refined by a bounded scalar search of |c(tau)| within one grid step of it.
+    Never above the strict mismatch (tau = 0, phi = 0 is a candidate)."""
+    from scipy.optimize import minimize_scalar
+    aa = inner(a, a, S, df, kept)
+    bb = inner(b, b, S, df, kept)
+    if aa <= 0.0 or bb <= 0.0:
+        return 0.0
+    k = np.nonzero(kept)[0]
+    if k.size == 0:
+        return 0.0
+    z = np.zeros(n_grid, dtype=np.complex128)
+    np.add.at(z, k % n_grid, a[k] * np.conj(b[k]) / S[k])
+    c = np.fft.ifft(z) * n_grid  # c[n] = c(n / n_grid)
+    n0 = int(np.argmax(np.abs(c)))
+    step = 1.0 / n_grid
+    res = minimize_scalar(lambda tau: -abs(overlap_vs_shift(a, b, S, kept, tau)),
+                          bounds=(n0 * step - step, n0 * step + step), method="bounded",
+                          options={"xatol": 1e-6 * step})
+    best = max(abs(c[n0]), -res.fun, abs(overlap_vs_shift(a, b, S, kept, 0.0)))
+    return 1.0 - 4.0 * df * best / math.sqrt(aa * bb)
 
 
 # ------------------------------------------------------------ training pieces

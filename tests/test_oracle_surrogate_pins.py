@@ -88,6 +88,45 @@ def test_mismatch_small_phase_error_law():
     assert abs(mm - 0.5 * (var_w + m * m)) < 1e-3 * mm
 
 
+def test_maximised_mismatch_removes_time_shift_and_phase():
+    h, S_, kept = _toy_signal()
+    df = 0.25
+    k = np.arange(h.shape[0])
+    assert abs(S.mismatch_maximised(h, h, S_, df, kept)) < 1e-12
+    # a phase offset and a time shift off the search grid are both undone
+    tau0 = 0.123456789  # in window lengths
+    g = 2.5 * h * np.exp(0.7j) * np.exp(-2j * np.pi * k * tau0)
+    assert S.mismatch(g, h, S_, df, kept) > 0.5
+    assert abs(S.mismatch_maximised(g, h, S_, df, kept)) < 1e-10
+    assert abs(S.mismatch_maximised(h, g, S_, df, kept)) < 1e-10
+
+
+def test_maximised_mismatch_bounds_and_brute_force():
+    h, S_, kept = _toy_signal(256)
+    df = 0.25
+    rs = np.random.default_rng(5)
+    g = h * np.exp(1j * 0.05 * rs.standard_normal(h.shape[0]))
+    strict = S.mismatch(g, h, S_, df, kept)
+    best = S.mismatch_maximised(g, h, S_, df, kept)
+    assert 0.0 <= best <= strict
+    # brute force: |c| on a direct grid of shifts over the whole window, then
+    # on a second direct grid of the same size around the first's best
+    kk = np.nonzero(kept)[0]
+    z = g[kk] * np.conj(h[kk]) / S_[kk]
+
+    def cmax(taus):
+        c = np.abs(np.exp(2j * np.pi * np.outer(taus, kk)) @ z)
+        return taus[np.argmax(c)], c.max()
+
+    t0, _ = cmax(np.linspace(0.0, 1.0, 20001))
+    _, cm = cmax(np.linspace(t0 - 5e-5, t0 + 5e-5, 20001))
+    aa = np.sum(np.abs(g[kk]) ** 2 / S_[kk])
+    bb = np.sum(np.abs(h[kk]) ** 2 / S_[kk])
+    brute = 1.0 - cm / math.sqrt(aa * bb)
+    assert best <= brute + 1e-12  # the search finds at least the grid's best
+    assert brute - best < 1e-10   # and no more than the fine grid's
+
+
 def test_interp_nodes_exact_for_linear_in_log_mf():
     Mf = S.node_grid()
     vals = 3.0 + 2.0 * np.log(Mf)
