@@ -505,9 +505,23 @@ gw_status gw_surrogate_waveform(gw_surrogate* s, const double* params, const flo
 /* noise-weighted mismatch 1 - <a|b>/sqrt(<a|a><b|b>), <a|b> = 4 df Re sum
  * a conj(b)/S over f_min <= f_k < f_cut (IMR-form cut from params, or all
  * bins below Nyquist if params is NULL), 0 < k < N/2.  ha, hb interleaved
- * complex float [B][N/2+1]; psd float [N/2+1]; mm double [B]. */
+ * complex float [B][N/2+1]; psd float [N/2+1]; mm double [B]; all device
+ * memory owned by the caller.  B = 0 returns GW_OK without reading any
+ * buffer (they may be NULL); a NULL buffer otherwise is GW_EINVAL. */
 gw_status gw_mismatch(gw_ctx* ctx, const float* ha, const float* hb, const float* psd, const double* params,
                       int64_t B, double* mm, hipStream_t stream);
+/* The same mismatch maximised over a time shift t and a phase offset phi of
+ * hb (the reported surrogate accuracy, beside the strict value above):
+ * 1 - max over t, phi of <a|b e^{i phi - 2 pi i f t}>/sqrt(<a|a><b|b>), with
+ * t over one window (the overlap has period T in t).  The best of the N/2
+ * shifts t = n T/(N/2) (one inverse transform of the weighted products) is
+ * refined by three parabolic steps (spacings 1, 1/4 and 1/16 of a shift) on
+ * the directly summed overlap (binary64 sums).  The zero shift is always a
+ * candidate, so the result is at most gw_mismatch's up to rounding.  Same
+ * arguments, layouts and ownership as gw_mismatch; B = 0 launches nothing.
+ * GW_EUNSUPPORTED for binary64 transforms (precision 2) or N > 32768. */
+gw_status gw_mismatch_max(gw_ctx* ctx, const float* ha, const float* hb, const float* psd, const double* params,
+                          int64_t B, double* mm, hipStream_t stream);
 /* Bytes of workspace gw_generate_batch_surrogate needs for batch size B. */
 gw_status gw_workspace_size_surrogate(const gw_ctx* ctx, int64_t B, int64_t* bytes);
 /* gw_generate_batch with the waveform taken from the surrogate: prior draws,

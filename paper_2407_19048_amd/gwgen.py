@@ -34,7 +34,7 @@ EXPORTS = ("gw_create", "gw_destroy", "gw_strerror", "gw_last_error", "gw_query"
            "gw_surrogate_fit_skip", "gw_surrogate_standardise", "gw_surrogate_forward",
            "gw_surrogate_gradients", "gw_surrogate_train_step", "gw_surrogate_hidden",
            "gw_surrogate_set_head", "gw_surrogate_fit_head", "gw_surrogate_nodes",
-           "gw_surrogate_waveform", "gw_mismatch", "gw_surrogate_save", "gw_surrogate_load",
+           "gw_surrogate_waveform", "gw_mismatch", "gw_mismatch_max", "gw_surrogate_save", "gw_surrogate_load",
            "gw_surrogate_set_state", "gw_workspace_size_surrogate", "gw_generate_batch_surrogate",
            "gw_graph_create", "gw_graph_launch", "gw_graph_set_batch", "gw_graph_last_error",
            "gw_graph_destroy", "gw_set_tuning", "gw_get_tuning", "gw_autotune",
@@ -111,6 +111,7 @@ def lib():
             "gw_surrogate_nodes": ([vp, vp, i64, vp, vp, vp], i32),
             "gw_surrogate_waveform": ([vp, vp, vp, i64, vp, vp, vp], i32),
             "gw_mismatch": ([vp, vp, vp, vp, vp, i64, vp, vp], i32),
+            "gw_mismatch_max": ([vp, vp, vp, vp, vp, i64, vp, vp], i32),
             "gw_surrogate_save": ([vp, ctypes.c_char_p], i32),
             "gw_surrogate_load": ([vp, ctypes.c_char_p], i32),
             "gw_surrogate_set_state": ([vp, vp, vp, vp, vp, vp, vp], i32),
@@ -334,6 +335,17 @@ class Generator:
         _want(mm, torch.float64, (B,), "mm")
         self._check(lib().gw_mismatch(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
                                       _stream()), "gw_mismatch")
+
+    def mismatch_max(self, ha, hb, psd, params, mm):
+        """Mismatch maximised over a time and a phase shift (see gw_mismatch_max)."""
+        import torch
+        B = ha.shape[0]
+        _want(ha, torch.complex64, (B, self.sizes["F"]), "ha")
+        _want(hb, torch.complex64, (B, self.sizes["F"]), "hb")
+        _want(psd, torch.float32, (self.sizes["F"],), "psd")
+        _want(mm, torch.float64, (B,), "mm")
+        self._check(lib().gw_mismatch_max(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
+                                          _stream()), "gw_mismatch_max")
 
     def alloc_workspace_surrogate(self, B, device="cuda"):
         import torch

@@ -230,8 +230,10 @@ class Surrogate:
         return dict(seconds_data=t_data, seconds_train=t_train, steps=total, initial_mse=initial_mse,
                     final_mse=self.history[-1], weight_decay=weight_decay, head=head_stats)
 
-    def mismatch_vs_plain(self, params, psd):
-        """(mm float64 [B], predicted log10 mm float32 [B]) against the plain model."""
+    def mismatch_vs_plain(self, params, psd, maximised=False):
+        """(mm float64 [B], predicted log10 mm float32 [B]) against the plain
+        model; with maximised, the mismatch minimised over a time shift and a
+        phase offset (gw_mismatch_max) is appended as a third tensor."""
         import torch
         B = params.shape[1]
         F = self.gen.sizes["F"]
@@ -246,7 +248,11 @@ class Surrogate:
         self.gen.gen_fd_waveform(params, hp, hx)
         mm = torch.empty(B, dtype=torch.float64, device="cuda")
         self.gen.mismatch(hs, hp, psd, params, mm)
-        return mm, logmm
+        if not maximised:
+            return mm, logmm
+        mm_max = torch.empty_like(mm)
+        self.gen.mismatch_max(hs, hp, psd, params, mm_max)
+        return mm, logmm, mm_max
 
     def fit_mismatch_head(self, seed, n, psd):
         import torch

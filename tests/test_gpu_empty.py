@@ -49,6 +49,10 @@ def test_steps_with_empty_batch(setup):
     psd = _e(0, 3, z["Fw"])
     gen.welch_psd(bg, offs, psd)
     gen.whiten(strain, psd, _e(0, 3, z["N"]), _e(0, dtype=torch.int32))
+    _say("mismatch, strict and maximised, B = 0")
+    S = torch.ones(z["F"], device=DEV)
+    gen.mismatch(hp, hc, S, params, _e(0, dtype=torch.float64))
+    gen.mismatch_max(hp, hc, S, params, _e(0, dtype=torch.float64))
     torch.cuda.synchronize()
 
 

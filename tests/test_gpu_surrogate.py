@@ -198,9 +198,10 @@ def test_trained_surrogate_mismatch_and_gain(gen, trained):
     s, psd, stats = trained
     B = 8192
     p = _params_gpu(gen, 4, B)  # held-out draws (different seed)
-    mm, logmm = s.mismatch_vs_plain(p, psd)
+    mm, logmm, mm_max = s.mismatch_vs_plain(p, psd, maximised=True)
     torch.cuda.synchronize()
     mm = mm.cpu().numpy()
+    mm_max = mm_max.cpu().numpy()
     pred = logmm.cpu().numpy()
     fallback = pred > -3.0
     med, p90 = np.median(mm), np.percentile(mm, 90)
@@ -228,6 +229,9 @@ def test_trained_surrogate_mismatch_and_gain(gen, trained):
     t_surr = ev[1].elapsed_time(ev[2]) / 5
     _say("mismatch over %d held-out draws: median %.2e  p90 %.2e  max %.2e; fallback rate %.3f; "
          "median after fallback %.2e" % (B, med, p90, mm.max(), fallback.mean(), med_kept))
+    _say("maximised over t_c and phi_c: median %.2e  p90 %.2e" % (np.median(mm_max), np.percentile(mm_max, 90)))
+    # the zero shift is a candidate of the maximisation
+    assert np.all(mm_max <= mm + 1e-9)
     _say("waveform stage B=%d: plain %.3f ms, surrogate %.3f ms, gain %.2f" % (B, t_plain, t_surr, t_plain / t_surr))
     # what the trained network adds: the same state with the MLP's output
     # layer zeroed (coefficients from the linear skip path and the mean only)
