@@ -252,6 +252,47 @@ def test_trained_surrogate_mismatch_and_gain(gen, trained):
     assert stats["final_mse"] < 0.5 * stats["initial_mse"]
 
 
+def test_maximised_mismatch_of_trained_surrogate_sampled(gen, trained):
+    """The maximised mismatch at the benchmark's batch (8192 held-out draws),
+    16 sampled pairs against the oracle's maximisation of the same waveform
+    rows; every pair at most its strict value."""
+    s, psd, _ = trained
+    B = 8192
+    F = gen.sizes["F"]
+    p = _params_gpu(gen, 4, B)
+    nodes = torch.empty((B, 2, 1024), dtype=torch.float32, device=DEV)
+    s.nodes(p, nodes)
+    hs = torch.empty((B, F), dtype=torch.complex64, device=DEV)
+    hsx = torch.empty_like(hs)
+    s.waveform(p, nodes, hs, hsx)
+    hp = torch.empty_like(hs)
+    hx = torch.empty_like(hs)
+    gen.gen_fd_waveform(p, hp, hx)
+    mm = torch.empty(B, dtype=torch.float64, device=DEV)
+    mx = torch.empty(B, dtype=torch.float64, device=DEV)
+    gen.mismatch(hs, hp, psd, p, mm)
+    gen.mismatch_max(hs, hp, psd, p, mx)
+    torch.cuda.synchronize()
+    mm, mx = mm.cpu().numpy(), mx.cpu().numpy()
+    assert np.all(mx <= mm + 1e-9)
+    P = p.cpu().numpy()
+    S_ = psd.cpu().numpy().astype(np.float64)
+    f = np.arange(F) / 8.0
+    k = np.arange(F)
+    idx = np.random.Generator(np.random.PCG64(17)).choice(B, 16, replace=False)
+    worst = 0.0
+    for i in idx:
+        _, _, Ms = oracle.waveform.mass_terms(P[0, i], P[1, i])
+        kept = (f >= 20.0) & (k > 0) & (k < F - 1) & (f < 0.2 / Ms)
+        a = hs[i].cpu().numpy().astype(np.complex128)
+        b = hp[i].cpu().numpy().astype(np.complex128)
+        ref = OS.mismatch_maximised(a, b, S_, 1.0 / 8.0, kept)
+        worst = max(worst, abs(mx[i] - ref))
+        assert abs(mx[i] - ref) <= 1e-7, (i, mx[i], ref)
+    _say("maximised mismatch B=%d: median %.2e (strict %.2e); 16 sampled pairs within %.1e of the oracle"
+         % (B, np.median(mx), np.median(mm), worst))
+
+
 def test_save_and_load_roundtrip(gen, trained, tmp_path):
     s, psd, _ = trained
     path = str(tmp_path / "surr.bin")
