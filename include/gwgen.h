@@ -70,7 +70,7 @@ typedef int32_t gw_status;
  * stretch preceding the window.  L = fftlen*fs is the Welch segment length and
  * S = (fftlen - overlap)*fs is the segment stride.  K = (P - L)/S + 1
  * segments are averaged.  Constraints: N and L are powers of two,
- * 2^12 <= N <= 2^20, 2^11 <= L <= 2^12, N/L is an integer, and
+ * 2^11 <= N <= 2^20, 2^11 <= L <= 2^12, N/L is an integer, and
  * (P - L) is a multiple of S.  The stride must be L/2 (50 % overlap).
  * Precision mode 2 allows N up to 2^14 (gw_create returns GW_EUNSUPPORTED
  * above).  Windows longer than 2^15 samples run as a four-step transform

@@ -205,7 +205,7 @@ template <int NC> struct FftPlan {
   static constexpr int RL = NC / (NP16 == 4 ? 65536 : NP16 == 3 ? 4096 : NP16 == 2 ? 256 : 16);
   static constexpr int NPASS = NP16 + (RL > 1 ? 1 : 0);
   static constexpr int NT = NC / 16;
-  static_assert(NC == 2048 || NC == 4096 || NC == 8192 || NC == 16384, "unsupported FFT size");
+  static_assert(NC == 1024 || NC == 2048 || NC == 4096 || NC == 8192 || NC == 16384, "unsupported FFT size");
 };
 
 template <int NC, int PASS, int ORD = 0> struct PassInfo {

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
 
 // Second launch bound: minimum waves per SIMD (clamped to what LDS allows);
 // 4 waves per SIMD gives a budget of 128 VGPRs.
-template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : 8; };
+template <int NC> struct WinOcc { static constexpr int value = NC >= 16384 ? 1 : NC >= 8192 ? 4 : NC >= 2048 ? 8 : 16; };
 
 template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
 __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a) {
@@ -519,10 +519,10 @@ gw_status validate_cfg(const gw_config* g, DevCfg* dc, std::string* why) {
   if (!integral(Nd) || !integral(Pd) || !integral(Ld) || !integral(Sd))
     return bad("t_window, psd_length, fftlen and overlap must be whole numbers of samples");
   const int64_t N = std::llround(Nd), P = std::llround(Pd), L = std::llround(Ld), S = std::llround(Sd);
-  // the window transforms run NC = N/2 in {2048, ..., 16384} points in one
+  // the window transforms run NC = N/2 in {1024, ..., 16384} points in one
   // workgroup (four-step beyond): shorter windows have no kernel
-  if (!is_pow2(N) || N < 4096 || N > (int64_t(1) << 20))
-    return bad("N = t_window*fs must be a power of two in [4096, 2^20]");
+  if (!is_pow2(N) || N < 2048 || N > (int64_t(1) << 20))
+    return bad("N = t_window*fs must be a power of two in [2048, 2^20]");
   if (N > 32768 && g->precision == 2) return GW_EUNSUPPORTED;
   if (!is_pow2(L) || L < 2048 || L > 4096) return bad("L = fftlen*fs must be 2048 or 4096");
   if (S * 2 != L) return bad("overlap must be half of fftlen (stride L/2)");
@@ -641,6 +641,7 @@ template <class T, class TP, bool FULL, int SRC, int ORD>
 static void launch_window_ord(const DevCfg& d, int64_t blocks, const WinArgs& a, hipStream_t stream) {
   const int NC = d.N / 2;
   switch (NC) {
+    case 1024: hipLaunchKernelGGL((k_window<T, TP, FULL, 1024, SRC, ORD>), dim3(unsigned(blocks)), dim3(64), 0, stream, a); break;
     case 2048: hipLaunchKernelGGL((k_window<T, TP, FULL, 2048, SRC, ORD>), dim3(unsigned(blocks)), dim3(128), 0, stream, a); break;
     case 4096: hipLaunchKernelGGL((k_window<T, TP, FULL, 4096, SRC, 0>), dim3(unsigned(blocks)), dim3(256), 0, stream, a); break;
     case 8192: hipLaunchKernelGGL((k_window<T, TP, FULL, 8192, SRC, ORD>), dim3(unsigned(blocks)), dim3(512), 0, stream, a); break;
@@ -708,6 +709,7 @@ template <class T>
 static void launch_filter(const DevCfg& d, const FiltArgs& a, hipStream_t stream) {
   const dim3 grid = dim3(unsigned(d.n_det));
   switch (d.N / 2) {
+    case 1024: hipLaunchKernelGGL((k_filter<T, 1024>), grid, dim3(64), 0, stream, a); break;
     case 2048: hipLaunchKernelGGL((k_filter<T, 2048>), grid, dim3(128), 0, stream, a); break;
     case 4096: hipLaunchKernelGGL((k_filter<T, 4096>), grid, dim3(256), 0, stream, a); break;
     case 8192: hipLaunchKernelGGL((k_filter<T, 8192>), grid, dim3(512), 0, stream, a); break;

@@ -52,6 +52,9 @@ CONFIGS["bns_long"] = dict(
     det_ids=(0, 1, 2), fs=2048.0, t_window=256.0, psd_length=64.0, fftlen=2.0, overlap=1.0,
     f_min=20.0, approximant=0, precision=1, mc=(1.0, 2.0), q=(0.5, 1.0), chi=(-0.05, 0.05),
     dl=(20.0, 300.0), batch=256, log2_bg=27)
+# the shortest window: 2 s at 1024 Hz (N = 2048, a 1024-point window
+# transform), otherwise the 64-signal TaylorF2 workload
+CONFIGS["pr1_short"] = dict(CONFIGS["pr1_plain"], t_window=2.0)
 CONFIGS["precision_study"] = dict(CONFIGS["paper_scale"], batch=8192)
 CONFIGS["surrogate"] = dict(CONFIGS["paper_scale"], batch=8192)
 

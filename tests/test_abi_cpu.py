@@ -55,7 +55,7 @@ def _create(cfg):
 
 @pytest.mark.parametrize("override", [
     dict(t_window=3.0),                 # N not a power of two
-    dict(t_window=2.0),                 # N = 2048: below the shortest window transform
+    dict(t_window=1.0),                 # N = 1024: below the shortest window transform
     dict(fs=1000.0),                    # N not a power of two
     dict(fftlen=1.0, overlap=0.5),      # L = 1024 below the minimum
     dict(overlap=0.5),                  # stride not L/2

@@ -4,7 +4,7 @@ bounded scalar search), on seeded pairs: plain IMR-form waveforms against a
 slightly different system delayed by an off-grid time and rotated by a phase;
 broadband random pairs (a sharp overlap peak, no frequency cut); an
 identical pair, a pure phase offset and an empty signal.  Window lengths of
-4096, 16384 and 32768 samples (transforms of 2048, 8192 and 16384 points)."""
+2048, 4096, 16384 and 32768 samples (transforms of 1024 to 16384 points)."""
 
 import sys
 
@@ -26,6 +26,7 @@ DEV = "cuda"
 TOL = 1e-7
 
 SHAPES = {
+    "2048": ("pr1_short", {}),
     "4096": ("pr1_plain", {}),
     "16384": ("paper_scale", {}),
     "32768": ("paper_scale", dict(t_window=16.0)),

@@ -110,7 +110,7 @@ def test_sample_params_empty_batch_is_noop():
 
 # --------------------------------------------------------------- per stage
 
-@pytest.mark.parametrize("name,B,log2", [("pr1_plain", 64, 20), ("paper_scale", 12, 22)])
+@pytest.mark.parametrize("name,B,log2", [("pr1_plain", 64, 20), ("pr1_short", 24, 20), ("paper_scale", 12, 22)])
 def test_stages_match_oracle(name, B, log2):
     _say("stages %s B=%d" % (name, B))
     cfg = inputs.config(name)
@@ -163,7 +163,7 @@ def check_fused_against_oracle(cfg, bg, out, params, offs, idx):
     return np.array(errs)
 
 
-@pytest.mark.parametrize("name,B,log2", [("pr1_plain", 64, 20), ("paper_scale", 16, 22)])
+@pytest.mark.parametrize("name,B,log2", [("pr1_plain", 64, 20), ("pr1_short", 24, 20), ("paper_scale", 16, 22)])
 def test_fused_batch_matches_oracle(name, B, log2):
     _say("fused %s B=%d" % (name, B))
     cfg = inputs.config(name)

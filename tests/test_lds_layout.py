@@ -15,7 +15,7 @@ import collections
 
 import pytest
 
-SIZES = (2048, 4096, 8192, 16384)
+SIZES = (1024, 2048, 4096, 8192, 16384)
 
 
 def plan(nc, order):
