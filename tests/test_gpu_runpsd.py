@@ -70,7 +70,8 @@ def _oracle_filter_inputs(cfg, n_chunks, M, log2=21):
     return bg_np, psd, filt
 
 
-@pytest.mark.parametrize("name,M", [("pr1_plain", 1024), ("paper_scale", 4096), ("paper_scale", 2)])
+@pytest.mark.parametrize("name,M", [("pr1_plain", 1024), ("pr1_short", 512), ("paper_scale", 4096),
+                                    ("paper_scale", 2)])
 def test_whiten_filter_matches_oracle(name, M):
     cfg = inputs.config(name)
     _, psd, ref = _oracle_filter_inputs(cfg, 3, M)
@@ -114,7 +115,8 @@ def _run_batch(gen, bg, filt, crop, B, seed=9, batch_index=1):
 
 
 @pytest.mark.parametrize("name,M,crop", [("paper_scale", 4096, 2048), ("pr1_plain", 1024, 512),
-                                         ("paper_scale", 4096, 0), ("paper_scale", 64, 8188)])
+                                         ("pr1_short", 512, 256), ("paper_scale", 4096, 0),
+                                         ("paper_scale", 64, 8188)])
 def test_runpsd_batch_matches_oracle(name, M, crop):
     cfg = inputs.config(name)
     bg_np, _, filt = _oracle_filter_inputs(cfg, 3, M)

@@ -39,7 +39,7 @@ def bg_for(name, log2):
     return _BG[key]
 
 
-@pytest.mark.parametrize("name", ["pr1_plain", "paper_scale"])
+@pytest.mark.parametrize("name", ["pr1_plain", "pr1_short", "paper_scale"])
 def test_view_pairs_match_oracle(name):
     cfg = inputs.config(name)
     bg_np = bg_for(name, 21)
