@@ -333,6 +333,8 @@ class Generator:
         _want(hb, torch.complex64, (B, self.sizes["F"]), "hb")
         _want(psd, torch.float32, (self.sizes["F"],), "psd")
         _want(mm, torch.float64, (B,), "mm")
+        if params is not None:
+            _want(params, torch.float64, (N_PARAMS, B), "params")
         self._check(lib().gw_mismatch(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
                                       _stream()), "gw_mismatch")
 
@@ -344,6 +346,8 @@ class Generator:
         _want(hb, torch.complex64, (B, self.sizes["F"]), "hb")
         _want(psd, torch.float32, (self.sizes["F"],), "psd")
         _want(mm, torch.float64, (B,), "mm")
+        if params is not None:
+            _want(params, torch.float64, (N_PARAMS, B), "params")
         self._check(lib().gw_mismatch_max(self._h, _ptr(ha), _ptr(hb), _ptr(psd), _ptr(params), B, _ptr(mm),
                                           _stream()), "gw_mismatch_max")
 
