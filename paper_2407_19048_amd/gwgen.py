@@ -187,6 +187,13 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _workspace_bytes(workspace):
+    """Size in bytes of a workspace tensor, which must be contiguous device memory."""
+    if workspace.device.type != "cuda" or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    return workspace.numel() * workspace.element_size()
+
+
 def _want(t, dtype, shape, name):
     import torch
     if t.device.type != "cuda":
@@ -304,9 +311,7 @@ class Generator:
             _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (B,), "status")
-        if workspace.device.type != "cuda" or not workspace.is_contiguous():
-            raise ValueError("workspace must be a contiguous device tensor")
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_generate_batch(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
                                             bg.shape[1], _ptr(out), _ptr(params_f32), _ptr(status),
                                             _ptr(workspace), nbytes, _stream()),
@@ -367,7 +372,7 @@ class Generator:
             _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (B,), "status")
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_generate_batch_surrogate(self._h, surrogate._h, int(seed), int(batch_index), int(B),
                                                       _ptr(bg), bg.shape[1], _ptr(out), _ptr(params_f32),
                                                       _ptr(status), ctypes.c_float(log10_mm_max),
@@ -399,7 +404,7 @@ class Generator:
             _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (B,), "status")
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_generate_batch_pairs(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
                                                   bg.shape[1], _ptr(out_ref), _ptr(out_shift), _ptr(params_f32),
                                                   _ptr(status), _ptr(workspace), nbytes, _stream()),
@@ -414,7 +419,7 @@ class Generator:
             _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (B,), "status")
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_generate_batch_oversampled(self._h, int(seed), int(batch_index), int(B), int(ext_k),
                                                         _ptr(bg), bg.shape[1], _ptr(out), _ptr(params_f32),
                                                         _ptr(status), _ptr(workspace), nbytes, _stream()),
@@ -453,7 +458,7 @@ class Generator:
             _want(params_f32, torch.float32, (N_PARAMS, B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (B,), "status")
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_generate_batch_runpsd(self._h, int(seed), int(batch_index), int(B), _ptr(bg),
                                                    bg.shape[1], _ptr(filt), int(crop), _ptr(out),
                                                    _ptr(params_f32), _ptr(status), _ptr(workspace), nbytes,
@@ -470,7 +475,7 @@ class Generator:
         if status is not None:
             _want(status, torch.int32, (B,), "status")
         h = ctypes.c_void_p()
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_graph_create(self._h, int(seed), int(first_batch), int(B), _ptr(bg), bg.shape[1],
                                           _ptr(out), _ptr(params_f32), _ptr(status), _ptr(workspace), nbytes,
                                           ctypes.byref(h)), "gw_graph_create")
@@ -487,9 +492,10 @@ class Generator:
     def autotune(self, B, bg, out, workspace, reps=5):
         """Pick the radix orders; returns the mean ms per variant."""
         import torch
+        _want(bg, torch.float32, (self.sizes["D"], bg.shape[1]), "bg")
         _want(out, torch.float32, (B, self.sizes["D"], self.sizes["N"]), "out")
         rep = (ctypes.c_double * 6)()
-        nbytes = workspace.numel() * workspace.element_size()
+        nbytes = _workspace_bytes(workspace)
         self._check(lib().gw_autotune(self._h, int(B), _ptr(bg), bg.shape[1], _ptr(out), _ptr(workspace), nbytes,
                                       int(reps), ctypes.cast(rep, ctypes.c_void_p)), "gw_autotune")
         return {"welch_ord0_occ2": rep[0], "welch_ord1_occ2": rep[1], "welch_ord0_occ3": rep[2],
@@ -602,9 +608,7 @@ class Ragged:
             _want(params_f32, torch.float32, (N_PARAMS, self.B), "params_f32")
         if status is not None:
             _want(status, torch.int32, (self.B,), "status")
-        if workspace.device.type != "cuda" or not workspace.is_contiguous():
-            raise ValueError("workspace must be a contiguous device tensor")
-        return workspace.numel() * workspace.element_size()
+        return _workspace_bytes(workspace)
 
     def generate(self, seed, batch_index, bgs, out, workspace, params_f32=None, status=None):
         nbytes = self._common(out, workspace, params_f32, status)

@@ -93,3 +93,9 @@ def test_null_context_rejected():
     assert L.gw_generate_batch(null, 1, 0, 4, null, 1 << 20, null, null, null, null, 0, null) == gwgen.GW_EINVAL
     assert L.gw_generate_batch_noalloc(null, 1, 0, 4, null, 1 << 20, null, null, null, null) == gwgen.GW_EINVAL
     assert L.gw_destroy(null) == gwgen.GW_OK
+
+
+def test_workspace_must_be_contiguous_device_memory():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        gwgen._workspace_bytes(torch.empty(64, dtype=torch.float64))  # host memory
