@@ -116,8 +116,8 @@ struct WinArgs {
   const float* logmm;     // [B] predicted log10 mismatch (SRC 3)
   float logmm_max;        // fallback threshold (SRC 3)
   int crop;               // samples dropped at each end of the output (SRC 4; even)
-  int ref_view;           // SRC 1: signal at t_ref instead of the sample's t_c
-  double t_ref;
+  float* out2;            // SRC 5: the reference views [B][D][N]
+  double t_ref;           // SRC 5: the reference view's signal time
 };
 
 // Surrogate node grid: 1024 points log-spaced in Mf over [2e-3, 0.2].
@@ -242,16 +242,20 @@ __device__ __forceinline__ cpx<T> signal_bin_surr(const DevCfg& cf, const WinArg
 // from surrogate node values (plain model where the predicted mismatch
 // exceeds the threshold).  SRC 2: inject (hrow = hdet row, nz = noise window).
 // SRC 4: as SRC 1 whitened with a fixed per-run filter (psd = filter row of
-// N/2 + 1 gains), storing samples [crop, N - crop) only.
+// N/2 + 1 gains), storing samples [crop, N - crop) only.  SRC 5: the view
+// pair of one item: as SRC 1 into o, then, from the same noise spectrum kept
+// in registers, the same window with the signal at t_ref into o2.
 // `active` false: compute on the given (valid) item but store nothing, so
 // that idle sub-blocks still meet every block barrier.
 template <class T, class TP, bool FULL, int NC, int SRC, int ORD>
 __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, int t, int64_t b, int d,
                                             const float* x, const float* hrow, const float* nz, const float* psd,
                                             float* o, const cpx<T>* twtab, const cpx<T>* twr, T* sre, T* sim,
-                                            bool active, uint32_t* sflag, float* snodes = nullptr) {
+                                            bool active, uint32_t* sflag, float* snodes = nullptr,
+                                            float* o2 = nullptr) {
   constexpr int NT = NC / 16;
-  static_assert(SRC >= 0 && SRC <= 4, "source");
+  static_assert(SRC >= 0 && SRC <= 5, "source");
+  constexpr bool SIG = SRC == 1 || SRC == 5;  // in-register plain-model signal
   PowTwiddle<T, NC, ORD> tw{twtab};
   if constexpr (SRC == 3) {
     // the sample's node values go to LDS once (snodes: 2 x 1024 floats of
@@ -283,11 +287,17 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     }
     lds_barrier();
   }
+  // SRC 5: this thread's share of the noise spectrum, for the second view
+  cpx<T> keep[SRC == 5 ? 16 : 1];
+  if constexpr (SRC == 5) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) keep[e] = v[e];
+  }
 
   T cpl = T(0), cxx = T(0);
   double tauT = 0.0;
   WfScalars wsh;
-  if constexpr (SRC == 1 || SRC == 3 || SRC == 4) wsh = load_const(a.wf + b);
+  if constexpr (SIG || SRC == 3 || SRC == 4) wsh = load_const(a.wf + b);
   bool use_surr = false;
   lds_cfptr nd = nullptr;
   if constexpr (SRC == 3) {
@@ -297,14 +307,13 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     if (active && !use_surr && t == 0 && d == 0 && a.status)
       atomicOr(a.status + b, uint32_t(GW_STATUS_SURROGATE_FALLBACK));
   }
-  if constexpr (SRC == 1 || SRC == 3 || SRC == 4) {
+  double tauT_ref = 0.0;  // SRC 5: the reference view's time shift
+  if constexpr (SIG || SRC == 3 || SRC == 4) {
     const DetScalars dsh = load_const(a.dsc + (b * cf.n_det + d));
     cpl = T(dsh.fp * 0.5 * (1.0 + wsh.cosi * wsh.cosi));
     cxx = T(dsh.fx * wsh.cosi);
     tauT = dsh.tau * cf.invT;
-    if constexpr (SRC == 1) {
-      if (a.ref_view) tauT = (dsh.tau - wsh.tc + a.t_ref) * cf.invT;  // same delays, signal at t_ref
-    }
+    if constexpr (SRC == 5) tauT_ref = (dsh.tau - wsh.tc + a.t_ref) * cf.invT;  // same delays, signal at t_ref
   }
   const float2* hsrc = reinterpret_cast<const float2*>(hrow);
 
@@ -361,7 +370,7 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       const cpx<T> u = cmul(W, csub(A, cconj(Bm)));
       cpx<T> Xk = {T(0.5) * (s.x + u.y), T(0.5) * (s.y - u.x)};
       cpx<T> Xm = {T(0.5) * (s.x - u.y), T(0.5) * (-s.y - u.x)};
-      if constexpr (SRC == 1 || SRC == 4) {
+      if constexpr (SIG || SRC == 4) {
         Xk = cadd(Xk, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, k));
         if (km != k) Xm = cadd(Xm, signal_bin<T, TP, FULL>(cf, a, wsh, cpl, cxx, tauT, km));
       } else if constexpr (SRC == 3) {
@@ -401,6 +410,8 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
     }
   };
 
+  // pairs, inverse transform and store of one output window ov
+  auto emit = [&](float* ov) {
   // pairs (k, NC - k) for k = t + NT i in [0, NC/2] (NC/2 = 8 NT): two per
   // loop trip, whose LDS reads are issued together and whose arithmetic
   // chains interleave; the last one (k = NC/2) belongs to thread 0 alone
@@ -440,13 +451,29 @@ __device__ __forceinline__ void window_item(const DevCfg& cf, const WinArgs& a, 
       if constexpr (SRC == 4) {
         // cropped store: samples [crop, N - crop), crop even
         const int m = n - (a.crop >> 1);
-        if (m >= 0 && m < NC - a.crop) reinterpret_cast<float2*>(o)[m] = y;
+        if (m >= 0 && m < NC - a.crop) reinterpret_cast<float2*>(ov)[m] = y;
       } else {
-        reinterpret_cast<float2*>(o)[n] = y;
+        reinterpret_cast<float2*>(ov)[n] = y;
       }
     }
-    if (flag) atomicOr(sflag, flag);
   }
+  };
+  emit(o);
+  if constexpr (SRC == 5) {
+    // reference view: the noise spectrum back to LDS, the signal at t_ref
+    lds_barrier();  // the inverse transform's last LDS reads are done
+    const int tk = fresh_lane(t);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = lpad<T>(fft_out_index<NC, ORD>(tk, e));
+      sre[i] = keep[e].x;
+      sim[i] = keep[e].y;
+    }
+    lds_barrier();
+    tauT = tauT_ref;
+    emit(o2);
+  }
+  if (active && flag) atomicOr(sflag, flag);
 }
 
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

@@ -169,9 +169,10 @@ __global__ __launch_bounds__(NC / 16, WinOcc<NC>::value) void k_window(WinArgs a
   } else x = a.src + int64_t(d) * a.L_bg + a.offset[b] + a.cf.P;
   const float* psd = SRC == 4 ? a.psd + int64_t(d) * (NC + 1) : a.psd + bd * a.cf.Fw;
   float* o = a.out + bd * (SRC == 4 ? N - 2 * a.crop : N);
+  float* o2 = SRC == 5 ? a.out2 + bd * N : nullptr;
   window_item<T, TP, FULL, NC, SRC, ORD>(a.cf, a, t, b, d, x, hrow, nz, psd, o,
                                          reinterpret_cast<const cpx<T>*>(a.tw), reinterpret_cast<const cpx<T>*>(a.twr),
-                                         lds, lds + LS, true, &sflag, SRC == 3 ? snodes : nullptr);
+                                         lds, lds + LS, true, &sflag, SRC == 3 ? snodes : nullptr, o2);
   __syncthreads();
   if (t == 0 && sflag && a.status) atomicOr(a.status + b, sflag);
 }
@@ -792,15 +793,16 @@ static gw_status enqueue_batch(gw_ctx* c, uint64_t seed, uint64_t batch_index, c
       if (out_ref) return fail(c, GW_EUNSUPPORTED, "view pairs need N <= 32768");
       return long_window(c, 1, a, bg, nullptr, B * c->dc.n_det, stream);
     }
-    launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
-    s = check_launch(c, "k_window<fused>");
-    if (s == GW_OK && out_ref) {
-      // reference view: same windows, PSDs and parameters, signal at t_ref
-      a.out = out_ref;
-      a.ref_view = 1;
+    if (out_ref) {
+      // view pairs: one pass, the reference view (same windows, PSDs and
+      // parameters, signal at t_ref) from the same noise spectrum
+      a.out2 = out_ref;
       a.t_ref = c->dc.T - 1.5;
+      launch_window_prec<5>(c->dc, B * c->dc.n_det, a, stream);
+      s = check_launch(c, "k_window<view pair>");
+    } else {
       launch_window_prec<1>(c->dc, B * c->dc.n_det, a, stream);
-      s = check_launch(c, "k_window<reference view>");
+      s = check_launch(c, "k_window<fused>");
     }
   }
   return s;
