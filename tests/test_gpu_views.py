@@ -132,3 +132,35 @@ def test_oversampling_rejects_bad_k():
     out = torch.empty((2, 2, gen.sizes["N"]), dtype=torch.float32, device=DEV)
     with pytest.raises(gwgen.GWError):
         gen.generate_batch_oversampled(1, 0, 2, 0, bg, out, gen.alloc_workspace(2))
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_view_pairs_in_other_precision_modes(prec):
+    """The one-pass view-pair kernel in binary32 throughout (0) and binary64
+    (2): the shifted view equals the plain batch bit for bit, and the
+    reference view follows the oracle (mode 2 to the output's binary32
+    rounding; mode 0 within the bound its binary32 phase allows)."""
+    name = "paper_scale"
+    cfg = inputs.config(name, precision=prec)
+    bg_np = bg_for(name, 21)
+    gen = gwgen.Generator(cfg)
+    B, D, N = 4, gen.sizes["D"], gen.sizes["N"]
+    bg = torch.from_numpy(bg_np).to(DEV)
+    ref_t = torch.empty((B, D, N), dtype=torch.float32, device=DEV)
+    shf_t = torch.empty_like(ref_t)
+    ws = gen.alloc_workspace(B)
+    _say("view pairs %s precision %d" % (name, prec))
+    gen.generate_batch_pairs(6, 2, B, bg, ref_t, shf_t, ws)
+    plain = torch.empty_like(ref_t)
+    gen.generate_batch(6, 2, B, bg, plain, gen.alloc_workspace(B))
+    torch.cuda.synchronize()
+    assert torch.equal(shf_t, plain)
+    p, o = priors.sample_params(cfg, 6, 2 * B, B, bg_np.shape[1])
+    got = ref_t.cpu().numpy()
+    worst = 0.0
+    for i in range(B):
+        d_ref, _ = pipeline.generate_pair(cfg, bg_np, p[:, i], int(o[i]))
+        for d in range(D):
+            worst = max(worst, rel_l2(got[i, d], d_ref[d]))
+    _say("view pairs precision %d: reference view worst rel L2 %.3e" % (prec, worst))
+    assert worst < (2e-7 if prec == 2 else 1e-2)
