@@ -293,6 +293,52 @@ def test_maximised_mismatch_of_trained_surrogate_sampled(gen, trained):
          % (B, np.median(mx), np.median(mm), worst))
 
 
+def test_inference_mlp_matches_layer_forward(gen, trained):
+    """Node values and predicted mismatch from the one-pass inference MLP
+    against the layer-by-layer forward's outputs (z from gw_surrogate_forward,
+    the last hidden layer from gw_surrogate_hidden) carried through the
+    coefficient and reconstruction formulas in binary64, at a batch that is
+    not a multiple of the 32-row tile."""
+    s, psd, _ = trained
+    B = 4096 + 13
+    p = _params_gpu(gen, 5, B)
+    theta = p[:4].t().float().contiguous()
+    z = torch.empty((B, GS.N_OUT), dtype=torch.float32, device=DEV)
+    s.forward(theta, z)
+    h3 = torch.empty((B, GS.HIDDEN), dtype=torch.float32, device=DEV)
+    s.hidden(theta, h3)
+    nodes = torch.empty((B, 2, 1024), dtype=torch.float32, device=DEV)
+    logmm = torch.empty(B, dtype=torch.float32, device=DEV)
+    s.nodes(p, nodes, logmm)
+    torch.cuda.synchronize()
+    basis, mean, A, zmean, zstd, head = s.get_state()
+    P = p.cpu().numpy()
+    feat = np.stack([OS.features(P[1, i], P[2, i], P[3, i]) for i in range(B)])
+    coef = feat @ A.astype(np.float64) + zstd.astype(np.float64) * z.cpu().numpy() + zmean.astype(np.float64)
+    ref = np.stack([mean[0] + coef[:, :64] @ basis[0].astype(np.float64),
+                    mean[1] + coef[:, 64:] @ basis[1].astype(np.float64)], axis=1)
+    got = nodes.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm((got - ref).reshape(B, -1), axis=1) / np.linalg.norm(ref.reshape(B, -1), axis=1)
+    lm_ref = h3.cpu().numpy().astype(np.float64) @ head[:GS.HIDDEN].astype(np.float64) + float(head[GS.HIDDEN])
+    lm_err = np.abs(logmm.cpu().numpy() - lm_ref).max()
+    _say("inference MLP: node values within %.2e (rel L2, worst row), predicted log10 mismatch within %.2e"
+         % (rel.max(), lm_err))
+    assert rel.max() < 2e-6
+    assert lm_err < 1e-4
+    # node stage time at the benchmark's batch
+    Bt = 8192
+    pt = _params_gpu(gen, 6, Bt)
+    nt = torch.empty((Bt, 2, 1024), dtype=torch.float32, device=DEV)
+    s.nodes(pt, nt)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(10):
+        s.nodes(pt, nt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    _say("node stage B=%d: %.4f ms" % (Bt, ev[0].elapsed_time(ev[1]) / 10))
+
+
 def test_save_and_load_roundtrip(gen, trained, tmp_path):
     s, psd, _ = trained
     path = str(tmp_path / "surr.bin")
